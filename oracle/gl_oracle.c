@@ -1,0 +1,219 @@
+/*
+ * Plain C float64 oracle of the preconditioned DCA inner solve for the graph
+ * Ginzburg-Landau model (arXiv 2303.14495).
+ *
+ * TEST INFRASTRUCTURE ONLY: called by the tests, the smoke check and the CPU
+ * baseline of the benchmark; never by the product library, and it shares no
+ * code with it.  The algorithm and its readings are those of gl_oracle.py:
+ *
+ *   normalized weights   what_ij = w_ij / sqrt(d_i d_j), d_i = sum_j w_ij
+ *                        (Section 2.2, L_s = I - D^{-1/2} W D^{-1/2})
+ *   DCA right-hand side  b = c u - (u^3 - u)/eps + eta Lambda y      (Prop. 1)
+ *   operator             T v = eps (v - What v) + eta Lambda v + c v  (Section 3)
+ *   sweep                v <- v + (b - T v) / g, all old values       (Section 3.1)
+ *                        finite step k: r = (u + k b) - (v + k T v)   (Lemma 1)
+ *   preconditioners      g from G_Jd,s / G_Jp,s / G_R,s or their k versions
+ *   energy               (eps/2) u.L_s u + sum (u^2-1)^2/(4 eps)
+ *                        + (eta/2) sum Lambda (u - y)^2               (Section 2.1)
+ *
+ * Rows are split over OpenMP threads; every row is summed in CSR order.
+ */
+#include <math.h>
+#include <stdint.h>
+#include <stdlib.h>
+#include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+enum { GLO_DAMPED_JACOBI = 0, GLO_PERTURBED_JACOBI = 1, GLO_RICHARDSON = 2 };
+
+static double *normalized(int64_t n, const int64_t *rp, const int32_t *col, const double *w)
+{
+    int64_t nnz = rp[n];
+    double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
+    double *wh = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!d || !wh) { free(d); free(wh); return NULL; }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        double s = 0.0;
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++) s += w[p];
+        d[i] = s;
+    }
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++)
+        for (int64_t p = rp[i]; p < rp[i + 1]; p++)
+            wh[p] = w[p] / sqrt(d[i] * d[col[p]]);
+    free(d);
+    return wh;
+}
+
+/* y_ik of node i (0 when unlabelled; K == 1: class 1 -> +1, class 0 -> -1). */
+static double target(int32_t label, int32_t K, int32_t k)
+{
+    if (label < 0) return 0.0;
+    if (K == 1) return label == 1 ? 1.0 : -1.0;
+    return label == k ? 1.0 : -1.0;
+}
+
+static double gdiag(int kind, double lam, double eps, double c, double eta,
+                    double delta0, double lmax, double k)
+{
+    double el = eta * lam;
+    if (isinf(k)) {
+        if (kind == GLO_DAMPED_JACOBI) return 2.0 * (eps + el + c);
+        if (kind == GLO_PERTURBED_JACOBI) return 2.0 * eps + el + c + delta0;
+        return eps * lmax + el + c + delta0;
+    }
+    if (kind == GLO_DAMPED_JACOBI) return 2.0 * (1.0 + k * (eps + c) + k * el);
+    if (kind == GLO_PERTURBED_JACOBI) return (2.0 * k * eps + 1.0) + k * (el + c) + delta0;
+    return 1.0 + k * (eps * lmax + el + c) + delta0;
+}
+
+/* Y = L_s X for n x K row-major X. */
+int glo_laplacian_apply(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+                        int32_t K, const double *X, double *Y)
+{
+    double *wh = normalized(n, rp, col, w);
+    if (!wh) return 1;
+#pragma omp parallel for schedule(static)
+    for (int64_t i = 0; i < n; i++) {
+        for (int32_t k = 0; k < K; k++) {
+            double z = 0.0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * X[(int64_t)col[p] * K + k];
+            Y[i * K + k] = X[i * K + k] - z;
+        }
+    }
+    free(wh);
+    return 0;
+}
+
+static void energy_cols(int64_t n, const int64_t *rp, const int32_t *col, const double *wh,
+                        int32_t K, const int32_t *labels, const double *U,
+                        double eps, double eta, double *out)
+{
+    double *lap = (double *)calloc((size_t)K, sizeof(double));
+    double *well = (double *)calloc((size_t)K, sizeof(double));
+    double *fid = (double *)calloc((size_t)K, sizeof(double));
+#pragma omp parallel for schedule(static) reduction(+ : lap[:K], well[:K], fid[:K])
+    for (int64_t i = 0; i < n; i++) {
+        for (int32_t k = 0; k < K; k++) {
+            double u = U[i * K + k], z = 0.0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * U[(int64_t)col[p] * K + k];
+            lap[k] += u * (u - z);
+            well[k] += (u * u - 1.0) * (u * u - 1.0);
+            if (labels[i] >= 0) {
+                double e = u - target(labels[i], K, k);
+                fid[k] += e * e;
+            }
+        }
+    }
+    for (int32_t k = 0; k < K; k++) out[k] = 0.5 * eps * lap[k] + well[k] / (4.0 * eps) + 0.5 * eta * fid[k];
+    free(lap); free(well); free(fid);
+}
+
+/*
+ * outer DCA steps of `sweeps` preconditioned sweeps.  U (n x K) holds u^0 on
+ * entry and u^T on exit.  energies ((outer+1) x K) and res_sq
+ * (outer x sweeps x K) may be NULL.  Returns 0 on success.
+ */
+int glo_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+              int32_t K, const int32_t *labels, double *U,
+              double eps, double c, double eta, int32_t precond,
+              int32_t outer, int32_t sweeps, double delta0, double lambda_max, double step_k,
+              double *energies, double *res_sq)
+{
+    double *wh = normalized(n, rp, col, w);
+    size_t cells = (size_t)n * (size_t)K;
+    double *b = (double *)malloc(sizeof(double) * (cells ? cells : 1));
+    double *V = (double *)malloc(sizeof(double) * (cells ? cells : 1));
+    double *Vn = (double *)malloc(sizeof(double) * (cells ? cells : 1));
+    double *rs = (double *)calloc((size_t)K, sizeof(double));
+    if (!wh || !b || !V || !Vn || !rs) {
+        free(wh); free(b); free(V); free(Vn); free(rs);
+        return 1;
+    }
+    int finite_k = !isinf(step_k);
+    for (int32_t t = 0; t < outer; t++) {
+        if (energies) energy_cols(n, rp, col, wh, K, labels, U, eps, eta, energies + (int64_t)t * K);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; i++) {
+            double lam = labels[i] >= 0 ? 1.0 : 0.0;
+            for (int32_t k = 0; k < K; k++) {
+                double u = U[i * K + k];
+                b[i * K + k] = c * u - (u * u * u - u) / eps + eta * lam * target(labels[i], K, k);
+                V[i * K + k] = u;
+            }
+        }
+        for (int32_t s = 0; s < sweeps; s++) {
+            for (int32_t k = 0; k < K; k++) rs[k] = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : rs[:K])
+            for (int64_t i = 0; i < n; i++) {
+                double lam = labels[i] >= 0 ? 1.0 : 0.0;
+                double g = gdiag(precond, lam, eps, c, eta, delta0, lambda_max, step_k);
+                for (int32_t k = 0; k < K; k++) {
+                    double z = 0.0;
+                    for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * V[(int64_t)col[p] * K + k];
+                    double v = V[i * K + k];
+                    double Tv = eps * (v - z) + eta * lam * v + c * v;
+                    double r = finite_k ? (U[i * K + k] + step_k * b[i * K + k]) - (v + step_k * Tv)
+                                        : b[i * K + k] - Tv;
+                    rs[k] += r * r;
+                    Vn[i * K + k] = v + r / g;
+                }
+            }
+            if (res_sq)
+                for (int32_t k = 0; k < K; k++) res_sq[((int64_t)t * sweeps + s) * K + k] = rs[k];
+            double *tmp = V; V = Vn; Vn = tmp;
+        }
+        memcpy(U, V, sizeof(double) * cells);
+    }
+    if (energies) energy_cols(n, rp, col, wh, K, labels, U, eps, eta, energies + (int64_t)outer * K);
+    free(wh); free(b); free(V); free(Vn); free(rs);
+    return 0;
+}
+
+/* Power method on L_s from x0 (n); writes the Rayleigh quotient of the final
+   unit vector to *rq and min(2, 1.01 rq) to *lambda_hat. */
+int glo_power(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+              const double *x0, int32_t iters, double *rq, double *lambda_hat)
+{
+    double *wh = normalized(n, rp, col, w);
+    double *x = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    double *y = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
+    if (!wh || !x || !y) { free(wh); free(x); free(y); return 1; }
+    double nrm = 0.0;
+    for (int64_t i = 0; i < n; i++) nrm += x0[i] * x0[i];
+    nrm = sqrt(nrm);
+    for (int64_t i = 0; i < n; i++) x[i] = x0[i] / nrm;
+    for (int32_t it = 0; it <= iters; it++) {
+        double ss = 0.0, xy = 0.0;
+#pragma omp parallel for schedule(static) reduction(+ : ss, xy)
+        for (int64_t i = 0; i < n; i++) {
+            double z = 0.0;
+            for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * x[col[p]];
+            y[i] = x[i] - z;
+            ss += y[i] * y[i];
+            xy += x[i] * y[i];
+        }
+        if (it == iters) {
+            *rq = xy;
+            break;
+        }
+        double inv = 1.0 / sqrt(ss);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; i++) x[i] = y[i] * inv;
+    }
+    *lambda_hat = fmin(2.0, 1.01 * *rq);
+    free(wh); free(x); free(y);
+    return 0;
+}
+
+int glo_num_threads(void)
+{
+#ifdef _OPENMP
+    return omp_get_max_threads();
+#else
+    return 1;
+#endif
+}
