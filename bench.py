@@ -1,0 +1,212 @@
+"""Benchmark of the preconditioned-DCA inner solve on one MI355X.
+
+Workload (default): the 2048 x 2048 textured-image segmentation graph
+(4 194 304 nodes, symmetrised 20-NN within a 15 x 15 window, self-tuning
+weights), K = 4 phases, 0.5 % labelled pixels, 10 DCA steps x 8 generalized-
+Richardson sweeps, weights stored in bf16 and the label field in f16 with
+f32 accumulation.  One step = one DCA solve (all sweeps with the fused
+right-hand side, update, energy and residual reductions) plus labelling, on an
+operator and a lambda_max estimate built once per graph (their times are
+reported separately).  The same solve with f32 storage, the roofline of the
+sweep kernel and the float64 CPU oracle on the host cores are reported beside
+it.
+
+    python bench.py [--gpus 1] [--steps 10] [--warmup 2] [--workload 4]
+"""
+
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "Laplacian-sweep HBM GB/s + DCA solves/s (FP32 vs BF16); served p50/p99 latency"
+DSIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
+
+
+def sweep_bytes(n, nnz, K, store_w, store_u, idx64=False):
+    """Algorithmic bytes of one sweep: index + weight streams, row offsets,
+    the compulsory read of the gathered field, the own-row read of u^t, the
+    write of the new field, and the labels."""
+    rp = 8 if idx64 else 4
+    return (nnz * (4 + DSIZE[store_w]) + rp * (n + 1) + 3 * n * K * DSIZE[store_u] + 4 * n)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--workload", type=int, default=4)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-fp32", action="store_true")
+    ap.add_argument("--sweep-reps", type=int, default=40)
+    return ap.parse_args()
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def timed_solves(op, labels, U, p, lam, steps, warmup):
+    import torch
+    import paper_2303_14495_amd as gl
+    kw = dict(eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=p.outer, sweeps=p.sweeps,
+              delta0=p.delta0, lambda_max=lam, step_k=p.step_k)
+    stats = torch.empty(gl.stats_length(U.shape[1], p.outer, p.sweeps), dtype=torch.float64,
+                        device=U.device)
+    for _ in range(warmup):
+        op.solve(labels, U, stats_out=stats, **kw)
+        gl.assign_labels(U)
+    torch.cuda.synchronize()
+    stream = torch.cuda.current_stream()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    t0 = time.perf_counter()
+    e0.record(stream)
+    for _ in range(steps):
+        op.solve(labels, U, stats_out=stats, **kw)
+        gl.assign_labels(U)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ev_ms = e0.elapsed_time(e1)
+    return wall, ev_ms, stats
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(json.dumps({"error": "this build runs on one GPU; --gpus must be 1",
+                          "n_gpus": args.gpus}))
+        sys.exit(2)
+    import numpy as np
+    import torch
+
+    import paper_2303_14495_amd as gl
+    from synth import make_problem
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    log(f"generating workload {args.workload}")
+    t = time.perf_counter()
+    p = make_problem(args.workload, device=dev)
+    log(f"  {p.name}: n={p.n} nnz={p.graph.nnz} K={p.K} ({time.perf_counter() - t:.1f} s)")
+    g = p.graph
+    labels = torch.from_numpy(p.labels).to(dev)
+    x0 = torch.from_numpy(np.random.default_rng(10_000 + p.seed).uniform(-1, 1, p.n)).to(
+        dev, torch.float32)
+
+    def run_variant(store_w, store_u, steps, warmup):
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op = gl.Operator(g.row_ptr, g.col, g.weight, store_w=store_w)
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - t0
+        lam = 2.0
+        t_power = 0.0
+        if p.precond == "richardson":
+            t0 = time.perf_counter()
+            _, lam = op.power_max_eig(x0, 150)
+            t_power = time.perf_counter() - t0
+        U = torch.from_numpy(p.u0).to(dev, gl.TORCH_DTYPES[store_u]).contiguous()
+        log(f"  {store_w}/{store_u}: operator {t_create * 1e3:.1f} ms, power method "
+            f"{t_power * 1e3:.1f} ms, lambda_hat {lam:.6f}")
+        U_first = U.clone()
+        op.solve(labels, U_first, eps=p.eps, c=p.c, eta=p.eta, precond=p.precond,
+                 outer=p.outer, sweeps=p.sweeps, delta0=p.delta0, lambda_max=lam,
+                 step_k=p.step_k, stats=False)
+        wall, ev_ms, stats = timed_solves(op, labels, U, p, lam, steps, warmup)
+        Ut = torch.from_numpy(p.u0).to(dev, gl.TORCH_DTYPES[store_u]).contiguous()
+        sweep_ms = gl.time_sweeps(op, labels, Ut, eps=p.eps, c=p.c, eta=p.eta,
+                                  precond=p.precond, delta0=p.delta0, lambda_max=lam,
+                                  step_k=p.step_k, reps=args.sweep_reps)
+        info = op.info()
+        B = sweep_bytes(p.n, g.nnz, p.K, store_w, store_u)
+        res = {
+            "solves_per_s": steps / wall,
+            "ms_per_solve": wall / steps * 1e3,
+            "ms_per_solve_events": ev_ms / steps,
+            "sweep_kernel_ms": sweep_ms,
+            "sweep_bytes": B,
+            "sweep_gbps": B / (sweep_ms * 1e-3) / 1e9,
+            "operator_create_ms": t_create * 1e3,
+            "power_method_ms": t_power * 1e3,
+            "lambda_hat": lam,
+            "lanes_per_row": info["lanes_per_row"],
+        }
+        labels_out = gl.assign_labels(U_first).cpu().numpy()
+        op.close()
+        return res, labels_out, U_first
+
+    sw, su = p.store_w, p.store_u
+    log(f"timing {sw}/{su}: {args.warmup} warmup + {args.steps} timed solves")
+    main_res, lab_main, U_main = run_variant(sw, su, args.steps, args.warmup)
+    fp32 = None
+    if not args.no_fp32 and (sw, su) != ("f32", "f32"):
+        log("timing f32/f32")
+        fp32, lab32, _ = run_variant("f32", "f32", args.steps, args.warmup)
+        fp32["label_agreement_with_main"] = float(np.mean(lab32 == lab_main))
+        fp32 = {k: fp32[k] for k in ("solves_per_s", "ms_per_solve", "sweep_kernel_ms",
+                                     "sweep_bytes", "sweep_gbps", "label_agreement_with_main")}
+    acc = float(np.mean(lab_main == p.truth))
+
+    cpu = None
+    if not args.no_cpu_baseline:
+        from oracle import c_oracle
+        rp, col, w = g.numpy()
+        log("CPU oracle sample: one DCA step of the same workload")
+        lam_cpu = main_res["lambda_hat"]
+        t0 = time.perf_counter()
+        c_oracle.dca_solve(p.n, rp, col, w, p.labels, p.u0, eps=p.eps, c=p.c, eta=p.eta,
+                           precond=p.precond, outer=1, sweeps=p.sweeps, delta0=p.delta0,
+                           lambda_max=lam_cpu, step_k=p.step_k, record=True)
+        t_step = time.perf_counter() - t0
+        cpu = {"value": 1.0 / (t_step * p.outer), "unit": "solves/s",
+               "cores": c_oracle.num_threads(), "kind": "oracle",
+               "sample": (f"1 of {p.outer} DCA steps ({p.sweeps} sweeps + 2 energy passes, "
+                          f"float64, C+OpenMP) on the full graph, {t_step:.2f} s, "
+                          f"scaled x{p.outer}")}
+
+    B = main_res["sweep_bytes"]
+    achieved = main_res["sweep_gbps"]
+    out = {
+        "metric": METRIC,
+        "value": main_res["solves_per_s"],
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": main_res["ms_per_solve"],
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "storage": {"weights": sw, "field": su},
+        "data": "synthetic",
+        "config": {"workload": p.name, "n": p.n, "nnz": g.nnz, "K": p.K,
+                   "outer_steps": p.outer, "sweeps": p.sweeps, "precond": p.precond,
+                   "eps": p.eps, "c": p.c, "eta": p.eta, "labelled_fraction": 0.005},
+        "sweep_gbps": achieved,
+        "sweep_kernel_ms": main_res["sweep_kernel_ms"],
+        "per_graph_setup_ms": {"operator_create": main_res["operator_create_ms"],
+                               "power_method_150": main_res["power_method_ms"]},
+        "accuracy_vs_ground_truth": acc,
+        "fp32": fp32,
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
+                     "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
+                     "kernel": "sweep_kernel", "bytes_per_launch": B},
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

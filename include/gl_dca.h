@@ -1,0 +1,205 @@
+/*
+ * gl_dca.h -- C ABI of the MI355X (gfx950) preconditioned-DCA library for the
+ * graph Ginzburg-Landau model of Shen, Sun and Tai, "Preconditioned DCA for
+ * the graph Ginzburg-Landau model" (arXiv 2303.14495).
+ *
+ * The library computes the inner linear solve of every DCA step,
+ *     (eps L_s + eta Lambda + c I) u^{t+1} = c u^t - (u^t^3 - u^t)/eps + eta Lambda y,
+ * by a fixed number of diagonal-preconditioned sweeps (Section 3, Prop. 1,
+ * and Section 3.1), on the normalized graph Laplacian
+ * L_s = I - D^{-1/2} W D^{-1/2} (Section 2.2), for an N x K label field.
+ *
+ * Conventions shared by every entry point
+ *   - Pointers named "device" point to GPU memory on the current HIP device;
+ *     pointers named "host" point to CPU memory.  The caller owns every buffer
+ *     it passes; the library never frees a caller buffer.
+ *   - `stream` is a hipStream_t passed as void* (NULL = the default stream).
+ *     Calls that do not say otherwise only enqueue work on `stream` and
+ *     return without synchronising.
+ *   - Dense N x K arrays are row-major: element (i, k) at i*K + k, and must be
+ *     16-byte aligned.
+ *   - Every entry point returns a gl_status; nothing aborts or throws across
+ *     the ABI.  On a non-OK status, gl_last_error() returns a message for the
+ *     calling thread.  Argument checks happen on the host before any launch.
+ *   - Arithmetic: storage in F64/F32/BF16/F16; accumulation in F32 (F64 when
+ *     the field is stored in F64).  BF16/F16 stores round to nearest even.
+ *   - Reductions have a fixed order: two runs with the same inputs give
+ *     bitwise identical outputs.
+ */
+#ifndef GL_DCA_H
+#define GL_DCA_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum gl_status {
+    GL_OK = 0,
+    GL_E_INVALID_ARG = 1,  /* a pointer, size, parameter or alignment is invalid */
+    GL_E_BAD_GRAPH = 2,    /* CSR malformed, not symmetric, self-loop, bad weight or degree */
+    GL_E_DTYPE = 3,        /* unsupported storage type or combination */
+    GL_E_NOMEM = 4,        /* a device or pinned-host allocation failed */
+    GL_E_BUDGET = 5,       /* (server) request larger than the HBM budget */
+    GL_E_NONFINITE = 6,    /* (server) a residual or energy became NaN/Inf */
+    GL_E_HIP = 7,          /* a HIP runtime call failed */
+    GL_E_QUEUE_FULL = 8,   /* (server) the pending queue is full */
+    GL_E_NOT_READY = 9,    /* (server) the result is not ready yet */
+    GL_E_CANCELLED = 10    /* (server) the request was cancelled */
+} gl_status;
+
+typedef enum gl_dtype { GL_F64 = 0, GL_F32 = 1, GL_BF16 = 2, GL_F16 = 3 } gl_dtype;
+
+/* Diagonal preconditioners G for T = eps L_s + eta Lambda + c I (Section 3.1):
+ *   DAMPED_JACOBI     G_Jd,s = 2(eps + c + eta Lambda)
+ *   PERTURBED_JACOBI  G_Jp,s = 2 eps + c + eta Lambda + delta0
+ *   RICHARDSON        G_R,s  = eps lambda_max + c + eta Lambda + delta0
+ * and, for a finite step size k, the preconditioners of T_k = I + k T of the
+ * same section (G_Jd,ks, G_Jp,ks, G_R,ks). */
+typedef enum gl_precond {
+    GL_PC_DAMPED_JACOBI = 0,
+    GL_PC_PERTURBED_JACOBI = 1,
+    GL_PC_RICHARDSON = 2
+} gl_precond;
+
+/* Weighted undirected graph in CSR form (Section 2.2), device memory.
+ *   row_ptr  int64 [n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
+ *   col_idx  int32 [nnz], strictly increasing within a row, in [0, n),
+ *            no self-loops (w_ii = 0, so diag(L_s) = 1)
+ *   weight   [nnz] of weight_dtype (GL_F64 or GL_F32), finite, > 0,
+ *            symmetric: w_ij == w_ji bit for bit with the same pattern
+ * Every degree d_i = sum_j w_ij must be > 0. */
+typedef struct gl_graph {
+    int64_t n;
+    int64_t nnz;
+    const int64_t *row_ptr;
+    const int32_t *col_idx;
+    const void *weight;
+    gl_dtype weight_dtype;
+} gl_graph;
+
+/* Solver parameters (Section 3 and Section 3.1).
+ *   eps > 0, c > 0, eta >= 0: the model's diffuse parameter, the convex-split
+ *     constant and the fidelity weight;
+ *   delta0 >= 0: the perturbation of G_Jp,s and G_R,s;
+ *   lambda_max in (0, 2]: the estimate of the largest eigenvalue of L_s used
+ *     by RICHARDSON (see gl_power_max_eig), ignored otherwise;
+ *   step_k: INFINITY for the DCA without step size (Prop. 1), or a finite
+ *     k > 0 for the step-size form T_k u = b_k, T_k = I + k T,
+ *     b_k = u^t + k b^t (Lemma 1);
+ *   outer_steps >= 0 DCA steps of inner_sweeps >= 1 sweeps each. */
+typedef struct gl_params {
+    double eps;
+    double c;
+    double eta;
+    double delta0;
+    double lambda_max;
+    double step_k;
+    int32_t precond;      /* gl_precond */
+    int32_t outer_steps;  /* T */
+    int32_t inner_sweeps; /* m */
+    int32_t reserved;     /* must be 0 */
+} gl_params;
+
+typedef struct gl_operator gl_operator;
+
+/* Build the normalized operator of `graph` (Section 2.2): validates the CSR
+ * (see gl_graph), computes d_i = sum_j w_ij in F64 and stores
+ * what_ij = w_ij / sqrt(d_i d_j) rounded to `store_w` (GL_F64, GL_F32,
+ * GL_BF16 or GL_F16) in library-owned device memory, with its own copy of the
+ * index arrays; the caller may free `graph`'s arrays after return.
+ * Synchronises `stream`.  Errors: GL_E_INVALID_ARG, GL_E_BAD_GRAPH (message
+ * names the first defect), GL_E_DTYPE, GL_E_NOMEM, GL_E_HIP. */
+gl_status gl_operator_create(const gl_graph *graph, gl_dtype store_w, void *stream,
+                             gl_operator **out);
+
+/* Release an operator (waits for nothing: the caller must not destroy an
+ * operator while work that uses it is still queued). NULL is accepted. */
+gl_status gl_operator_destroy(gl_operator *op);
+
+/* Host: number of nodes, stored nonzeros, weight storage type, lanes per
+ * row chosen for the sparse product, and device bytes held. */
+gl_status gl_operator_info(const gl_operator *op, int64_t *n, int64_t *nnz,
+                           gl_dtype *store_w, int32_t *lanes_per_row, size_t *device_bytes);
+
+/* Y = L_s X = X - D^{-1/2} W D^{-1/2} X (Section 2.2) for device X, Y of
+ * n x K elements of `dtype` (1 <= K <= 16); X and Y must not overlap. */
+gl_status gl_laplacian_apply(const gl_operator *op, int32_t K, gl_dtype dtype,
+                             const void *X, void *Y, void *stream);
+
+/* Device bytes of workspace that gl_power_max_eig needs (host out). */
+gl_status gl_power_workspace_size(const gl_operator *op, size_t *bytes);
+
+/* Power method for the largest eigenvalue of L_s (Section 3.1; Section 5.1.1
+ * uses 150 iterations): x <- x0/|x0|, then `iters` times
+ * x <- L_s x / |L_s x|, in F32 with F64 norms.  Host outputs:
+ * *rayleigh = x^T L_s x of the final unit vector, *lambda_hat =
+ * min(2, 1.01 * rayleigh), an upper estimate kept feasible by 2I >= L_s
+ * (Prop. 3).  x0: device float [n], not all zero.  Synchronises `stream`. */
+gl_status gl_power_max_eig(const gl_operator *op, int32_t iters, const float *x0,
+                           void *workspace, size_t workspace_bytes,
+                           double *rayleigh, double *lambda_hat, void *stream);
+
+/* Device bytes of workspace that gl_solve needs for K columns stored as
+ * `store_u` (host out). */
+gl_status gl_solve_workspace_size(const gl_operator *op, int32_t K, gl_dtype store_u,
+                                  size_t *bytes);
+
+/* Number of doubles gl_solve writes to `stats` for these parameters. */
+int64_t gl_stats_length(int32_t K, int32_t outer_steps, int32_t inner_sweeps);
+
+/* The preconditioned DCA (Prop. 1 with `inner_sweeps` diagonal sweeps per
+ * step, Section 3.1).  For t = 0 .. T-1:
+ *     b = c u^t - (u^t^3 - u^t)/eps + eta Lambda y          (right-hand side)
+ *     v = u^t; repeat m times: r = b - T v, v = v + r / g   (all old values)
+ *     u^{t+1} = v
+ * with T = eps L_s + eta Lambda + c I and g the diagonal of `precond`; for a
+ * finite step k, r = (u^t + k b) - (v + k T v) and g the T_k version.
+ *   labels  device int32 [n]: -1 unlabelled (Lambda_i = 0); otherwise
+ *           Lambda_i = 1 and, for K == 1, 1 -> y = +1 and 0 -> y = -1;
+ *           for K >= 2, y_ik = +1 if labels[i] == k else -1.
+ *   U       device [n x K] of `store_u`: u^0 on entry, u^T on return.
+ *   workspace  device, >= gl_solve_workspace_size bytes, 256-byte aligned.
+ *   stats   device double [gl_stats_length] or NULL (skips the reductions):
+ *           [0, (T+1)K)          F(u^t) per column, t = 0..T (Section 2.1)
+ *           [(T+1)K, +T m K)     |r|^2 per column for sweep s of step t
+ *           last element         1.0 if any of them is NaN/Inf, else 0.0
+ * Supported (store_w, store_u): F64 with F64; {F32, BF16, F16} with
+ * {F32, BF16, F16}.  Asynchronous; allocates nothing. */
+gl_status gl_solve(const gl_operator *op, const gl_params *params, int32_t K,
+                   const int32_t *labels, gl_dtype store_u, void *U,
+                   void *workspace, size_t workspace_bytes, double *stats, void *stream);
+
+/* Host-only check of a parameter block (the same checks gl_solve applies
+ * before launching anything).  GL_OK or GL_E_INVALID_ARG with a message. */
+gl_status gl_params_validate(const gl_params *params);
+
+/* Measurement helper: launch `reps` sweep kernels exactly as gl_solve launches
+ * its sweeps s >= 1 (gathering from one workspace buffer, writing the other,
+ * reading u^t = U on the own row, block partial sums on), bracketed by HIP
+ * events recorded on `stream`; *avg_ms (host) receives the mean kernel time.
+ * U is read, not changed; the workspace contents are overwritten.
+ * Synchronises `stream`. */
+gl_status gl_time_sweeps(const gl_operator *op, const gl_params *params, int32_t K,
+                         const int32_t *labels, gl_dtype store_u, const void *U,
+                         void *workspace, size_t workspace_bytes, int32_t reps,
+                         double *avg_ms, void *stream);
+
+/* Class per node from an n x K field: K == 1 -> 1 iff u_i >= 0, else 0;
+ * K >= 2 -> argmax_k u_ik, ties to the lowest k.  labels_out: device int32 [n]. */
+gl_status gl_assign_labels(int64_t n, int32_t K, gl_dtype dtype, const void *U,
+                           int32_t *labels_out, void *stream);
+
+/* Message of the last non-OK status returned to the calling thread. */
+const char *gl_last_error(void);
+
+/* Library version string. */
+const char *gl_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* GL_DCA_H */

@@ -1,0 +1,19 @@
+"""MI355X (gfx950) preconditioned DCA for the graph Ginzburg-Landau model.
+
+The solver is the HIP library ``libgl_dca.so`` (C ABI in include/gl_dca.h);
+this package holds its sources, its build script and a thin ctypes binding.
+"""
+
+from .gl import (  # noqa: F401
+    GLError,
+    Operator,
+    assign_labels,
+    load_library,
+    split_stats,
+    stats_length,
+    time_sweeps,
+    version,
+    DTYPES,
+    PRECONDS,
+    TORCH_DTYPES,
+)

@@ -1,0 +1,576 @@
+// C ABI of the gfx950 preconditioned-DCA library: operator construction,
+// Laplacian product, power method, the preconditioned DCA solve and labelling.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstdlib>
+#include <cstring>
+#include <string>
+
+#include "gl_internal.hpp"
+#include "gl_kernels.hpp"
+
+struct gl_operator {
+    int64_t n = 0, nnz = 0;
+    int device = 0;
+    gl_dtype store_w = GL_F32;
+    bool idx64 = false;
+    void* rp = nullptr;
+    int32_t* col = nullptr;
+    void* w = nullptr;
+    double* degree = nullptr;
+    int32_t G = 16, log2G = 4, tiles = 4, remap = 1;
+    size_t bytes = 0;
+};
+
+namespace {
+
+thread_local std::string g_err;
+
+gl_status fail(gl_status st, const std::string& msg) {
+    g_err = msg;
+    return st;
+}
+
+#define GL_HIP(expr, what)                                                                \
+    do {                                                                                  \
+        hipError_t e_ = (expr);                                                           \
+        if (e_ != hipSuccess) return fail(GL_E_HIP, std::string(what) + ": " + hipGetErrorString(e_)); \
+    } while (0)
+
+size_t dtype_size(int d) {
+    switch (d) {
+        case GL_F64: return 8;
+        case GL_F32: return 4;
+        case GL_BF16:
+        case GL_F16: return 2;
+        default: return 0;
+    }
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
+
+int env_int(const char* name, int dflt) {
+    const char* v = std::getenv(name);
+    return (v && *v) ? std::atoi(v) : dflt;
+}
+
+gl::RowLaunch row_launch(const gl_operator* op) {
+    gl::RowLaunch r;
+    r.rp = op->rp;
+    r.col = op->col;
+    r.w = op->w;
+    r.wdt = op->store_w;
+    r.idx64 = op->idx64;
+    r.n = op->n;
+    r.G = op->G;
+    r.log2G = op->log2G;
+    r.tiles = op->tiles;
+    r.remap = op->remap;
+    r.rows_per_block = (int64_t)(gl::kBlock >> op->log2G) * op->tiles;
+    r.grid = (op->n + r.rows_per_block - 1) / r.rows_per_block;
+    return r;
+}
+
+// Storage pairs the kernels are compiled for: F64 weights with an F64 field;
+// F32/BF16/F16 weights with an F32/BF16/F16 field.
+bool pair_ok(gl_dtype w, gl_dtype u) {
+    if (w == GL_F64 || u == GL_F64) return w == GL_F64 && u == GL_F64;
+    return dtype_size(w) != 0 && dtype_size(u) != 0;
+}
+
+hipError_t launch_sweep(gl_dtype u, int K, const gl::SweepLaunch& L, hipStream_t s) {
+    switch (u) {
+        case GL_F64: return gl::launch_sweep_f64(K, L, s);
+        case GL_F32: return gl::launch_sweep_f32(K, L, s);
+        case GL_BF16: return gl::launch_sweep_bf16(K, L, s);
+        case GL_F16: return gl::launch_sweep_f16(K, L, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t launch_laplacian(gl_dtype u, int K, const gl::RowLaunch& r, const void* x, void* y, hipStream_t s) {
+    switch (u) {
+        case GL_F64: return gl::launch_laplacian_f64(K, r, x, y, s);
+        case GL_F32: return gl::launch_laplacian_f32(K, r, x, y, s);
+        case GL_BF16: return gl::launch_laplacian_bf16(K, r, x, y, s);
+        case GL_F16: return gl::launch_laplacian_f16(K, r, x, y, s);
+    }
+    return hipErrorInvalidValue;
+}
+
+hipError_t copy_bytes(const void* src, void* dst, size_t bytes, hipStream_t s) {
+    if (bytes == 0) return hipSuccess;
+    const int64_t n16 = (int64_t)(bytes / 16);
+    const int32_t tail = (int32_t)(bytes % 16);
+    const int64_t work = n16 > tail ? n16 : tail;
+    const unsigned grid = (unsigned)((work + 255) / 256);
+    hipLaunchKernelGGL(gl::copy_bytes_kernel, dim3(grid), dim3(256), 0, s, (const gl::u32x4*)src,
+                       (gl::u32x4*)dst, n16, (const uint8_t*)src + n16 * 16, (uint8_t*)dst + n16 * 16, tail);
+    return hipGetLastError();
+}
+
+hipError_t fill_double(double* p, int64_t n, double v, hipStream_t s) {
+    if (n <= 0) return hipSuccess;
+    hipLaunchKernelGGL(gl::fill_double_kernel, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, s, p, n, v);
+    return hipGetLastError();
+}
+
+// g for unlabelled (lam = 0) and labelled (lam = 1) rows (Section 3.1).
+double precond_g(int kind, double lam, const gl_params& p) {
+    const double el = p.eta * lam;
+    if (std::isinf(p.step_k)) {
+        if (kind == GL_PC_DAMPED_JACOBI) return 2.0 * (p.eps + el + p.c);
+        if (kind == GL_PC_PERTURBED_JACOBI) return 2.0 * p.eps + el + p.c + p.delta0;
+        return p.eps * p.lambda_max + el + p.c + p.delta0;
+    }
+    const double k = p.step_k;
+    if (kind == GL_PC_DAMPED_JACOBI) return 2.0 * (1.0 + k * (p.eps + p.c) + k * el);
+    if (kind == GL_PC_PERTURBED_JACOBI) return (2.0 * k * p.eps + 1.0) + k * (el + p.c) + p.delta0;
+    return 1.0 + k * (p.eps * p.lambda_max + el + p.c) + p.delta0;
+}
+
+gl_status check_params(const gl_params* p) {
+    if (!p) return fail(GL_E_INVALID_ARG, "params is NULL");
+    auto fin = [](double x) { return std::isfinite(x); };
+    if (!fin(p->eps) || p->eps <= 0) return fail(GL_E_INVALID_ARG, "eps must be finite and > 0");
+    if (!fin(p->c) || p->c <= 0) return fail(GL_E_INVALID_ARG, "c must be finite and > 0");
+    if (!fin(p->eta) || p->eta < 0) return fail(GL_E_INVALID_ARG, "eta must be finite and >= 0");
+    if (!fin(p->delta0) || p->delta0 < 0) return fail(GL_E_INVALID_ARG, "delta0 must be finite and >= 0");
+    if (p->precond < GL_PC_DAMPED_JACOBI || p->precond > GL_PC_RICHARDSON)
+        return fail(GL_E_INVALID_ARG, "unknown preconditioner");
+    if (p->precond == GL_PC_RICHARDSON && (!fin(p->lambda_max) || p->lambda_max <= 0 || p->lambda_max > 2.0))
+        return fail(GL_E_INVALID_ARG, "lambda_max must lie in (0, 2] for the Richardson preconditioner");
+    if (std::isnan(p->step_k) || p->step_k <= 0 || (std::isinf(p->step_k) && p->step_k < 0))
+        return fail(GL_E_INVALID_ARG, "step_k must be > 0 or +INFINITY");
+    if (p->outer_steps < 0) return fail(GL_E_INVALID_ARG, "outer_steps must be >= 0");
+    if (p->inner_sweeps < 1) return fail(GL_E_INVALID_ARG, "inner_sweeps must be >= 1");
+    if (p->reserved != 0) return fail(GL_E_INVALID_ARG, "reserved must be 0");
+    return GL_OK;
+}
+
+template <typename TIN, typename TOUT, typename OffT>
+void launch_normalize(gl_operator* op, const gl_graph* g, hipStream_t s) {
+    const unsigned grid = (unsigned)((op->n + 1 + 255) / 256);
+    hipLaunchKernelGGL((gl::normalize_kernel<TIN, TOUT, OffT>), dim3(grid), dim3(256), 0, s, op->n, g->row_ptr,
+                       g->col_idx, static_cast<const TIN*>(g->weight), op->degree, static_cast<OffT*>(op->rp),
+                       op->col, static_cast<TOUT*>(op->w));
+}
+
+template <typename TIN, typename TOUT>
+void launch_normalize_idx(gl_operator* op, const gl_graph* g, hipStream_t s) {
+    if (op->idx64) launch_normalize<TIN, TOUT, int64_t>(op, g, s);
+    else launch_normalize<TIN, TOUT, int32_t>(op, g, s);
+}
+
+template <typename TIN>
+void launch_normalize_out(gl_operator* op, const gl_graph* g, hipStream_t s) {
+    switch (op->store_w) {
+        case GL_F64: launch_normalize_idx<TIN, double>(op, g, s); break;
+        case GL_F32: launch_normalize_idx<TIN, float>(op, g, s); break;
+        case GL_BF16: launch_normalize_idx<TIN, gl::bf16>(op, g, s); break;
+        case GL_F16: launch_normalize_idx<TIN, gl::f16>(op, g, s); break;
+    }
+}
+
+void free_op(gl_operator* op) {
+    if (!op) return;
+    (void)hipFree(op->rp);
+    (void)hipFree(op->col);
+    (void)hipFree(op->w);
+    (void)hipFree(op->degree);
+    delete op;
+}
+
+std::string bad_graph_message(int32_t flags, unsigned long long row) {
+    std::string m = "bad graph (first offending row " + std::to_string(row) + "):";
+    if (flags & gl::BAD_ROWPTR) m += " row_ptr not monotone or out of [0, nnz];";
+    if (flags & gl::BAD_COL_RANGE) m += " column index out of [0, n);";
+    if (flags & gl::BAD_COL_ORDER) m += " columns not strictly increasing within a row;";
+    if (flags & gl::BAD_SELF_LOOP) m += " self-loop;";
+    if (flags & gl::BAD_WEIGHT) m += " weight not finite and > 0;";
+    if (flags & gl::BAD_ASYMMETRIC) m += " W not symmetric (pattern or weight);";
+    if (flags & gl::BAD_DEGREE) m += " degree not finite and > 0;";
+    return m;
+}
+
+}  // namespace
+
+extern "C" {
+
+const char* gl_last_error(void) { return g_err.c_str(); }
+
+const char* gl_version(void) { return "gl_dca 0.1 (gfx950)"; }
+
+int64_t gl_stats_length(int32_t K, int32_t outer, int32_t sweeps) {
+    if (K < 1 || outer < 0 || sweeps < 1) return 0;
+    return (int64_t)(outer + 1) * K + (int64_t)outer * sweeps * K + 1;
+}
+
+gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, gl_operator** out) {
+    if (!g || !out) return fail(GL_E_INVALID_ARG, "graph and out must not be NULL");
+    *out = nullptr;
+    if (!g->row_ptr || !g->col_idx || !g->weight) return fail(GL_E_INVALID_ARG, "graph arrays must not be NULL");
+    if (g->n < 2 || g->n > INT32_MAX) return fail(GL_E_INVALID_ARG, "n must lie in [2, 2^31 - 1]");
+    if (g->nnz < 1 || g->nnz > ((int64_t)1 << 62)) return fail(GL_E_INVALID_ARG, "nnz must be >= 1");
+    if (g->weight_dtype != GL_F64 && g->weight_dtype != GL_F32)
+        return fail(GL_E_DTYPE, "input weights must be GL_F64 or GL_F32");
+    if (dtype_size(store_w) == 0) return fail(GL_E_DTYPE, "unknown store_w");
+    hipStream_t s = (hipStream_t)stream;
+
+    gl_operator* op = new gl_operator();
+    op->n = g->n;
+    op->nnz = g->nnz;
+    op->store_w = store_w;
+    op->idx64 = g->nnz > (int64_t)INT32_MAX;
+    if (hipGetDevice(&op->device) != hipSuccess) {
+        delete op;
+        return fail(GL_E_HIP, "hipGetDevice failed");
+    }
+    // geometry of the row kernels: G lanes per row from the mean row length
+    const double avg = (double)g->nnz / (double)g->n;
+    int G = 4;
+    while (G < 64 && 2.0 * G <= avg) G *= 2;
+    G = env_int("GL_LANES_PER_ROW", G);
+    if (G < 4 || G > 64 || (G & (G - 1))) G = 16;
+    op->G = G;
+    op->log2G = 0;
+    while ((1 << op->log2G) < G) ++op->log2G;
+    op->tiles = env_int("GL_TILES_PER_BLOCK", 4);
+    if (op->tiles < 1 || op->tiles > 64) op->tiles = 4;
+    op->remap = env_int("GL_XCD_REMAP", 1) ? 1 : 0;
+
+    const size_t rp_bytes = (size_t)(g->n + 1) * (op->idx64 ? 8 : 4);
+    const size_t col_bytes = (size_t)g->nnz * 4;
+    const size_t w_bytes = (size_t)g->nnz * dtype_size(store_w);
+    const size_t d_bytes = (size_t)g->n * 8;
+    void* scratch = nullptr;  // [int32 flags][pad][u64 first_bad][int64 rp0, rpn]
+    if (hipMalloc(&op->rp, rp_bytes) != hipSuccess || hipMalloc((void**)&op->col, col_bytes) != hipSuccess ||
+        hipMalloc(&op->w, w_bytes) != hipSuccess || hipMalloc((void**)&op->degree, d_bytes) != hipSuccess ||
+        hipMalloc(&scratch, 64) != hipSuccess) {
+        (void)hipFree(scratch);
+        free_op(op);
+        return fail(GL_E_NOMEM, "device allocation for the operator failed");
+    }
+    op->bytes = rp_bytes + col_bytes + w_bytes + d_bytes;
+    int32_t* d_flags = (int32_t*)scratch;
+    unsigned long long* d_first = (unsigned long long*)((char*)scratch + 8);
+    struct {
+        int32_t flags, pad;
+        unsigned long long first;
+    } init = {0, 0, ~0ull};
+    int64_t ends[2] = {-1, -1};
+    auto cleanup_fail = [&](gl_status st, const std::string& m) {
+        (void)hipStreamSynchronize(s);
+        (void)hipFree(scratch);
+        free_op(op);
+        return fail(st, m);
+    };
+    if (hipMemcpyAsync(scratch, &init, sizeof(init), hipMemcpyHostToDevice, s) != hipSuccess ||
+        hipMemcpyAsync(&ends[0], g->row_ptr, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipMemcpyAsync(&ends[1], g->row_ptr + g->n, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup_fail(GL_E_HIP, "copying row_ptr ends failed");
+    if (ends[0] != 0 || ends[1] != g->nnz)
+        return cleanup_fail(GL_E_BAD_GRAPH, "bad graph: row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
+
+    const unsigned grid = (unsigned)((g->n + 255) / 256);
+    if (g->weight_dtype == GL_F64) {
+        hipLaunchKernelGGL(gl::validate_kernel<double>, dim3(grid), dim3(256), 0, s, g->n, g->nnz, g->row_ptr,
+                           g->col_idx, (const double*)g->weight, d_flags, d_first);
+    } else {
+        hipLaunchKernelGGL(gl::validate_kernel<float>, dim3(grid), dim3(256), 0, s, g->n, g->nnz, g->row_ptr,
+                           g->col_idx, (const float*)g->weight, d_flags, d_first);
+    }
+    if (hipGetLastError() != hipSuccess) return cleanup_fail(GL_E_HIP, "validate launch failed");
+    if (hipMemcpyAsync(&init, scratch, sizeof(init), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup_fail(GL_E_HIP, "graph validation failed");
+    if (init.flags) return cleanup_fail(GL_E_BAD_GRAPH, bad_graph_message(init.flags, init.first));
+
+    if (g->weight_dtype == GL_F64) {
+        hipLaunchKernelGGL(gl::degree_kernel<double>, dim3(grid), dim3(256), 0, s, g->n, g->row_ptr,
+                           (const double*)g->weight, op->degree, d_flags, d_first);
+    } else {
+        hipLaunchKernelGGL(gl::degree_kernel<float>, dim3(grid), dim3(256), 0, s, g->n, g->row_ptr,
+                           (const float*)g->weight, op->degree, d_flags, d_first);
+    }
+    if (hipMemcpyAsync(&init, scratch, sizeof(init), hipMemcpyDeviceToHost, s) != hipSuccess ||
+        hipStreamSynchronize(s) != hipSuccess)
+        return cleanup_fail(GL_E_HIP, "degree computation failed");
+    if (init.flags) return cleanup_fail(GL_E_BAD_GRAPH, bad_graph_message(init.flags, init.first));
+
+    if (g->weight_dtype == GL_F64) launch_normalize_out<double>(op, g, s);
+    else launch_normalize_out<float>(op, g, s);
+    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+        return cleanup_fail(GL_E_HIP, "weight normalization failed");
+    (void)hipFree(scratch);
+    *out = op;
+    return GL_OK;
+}
+
+gl_status gl_params_validate(const gl_params* params) { return check_params(params); }
+
+gl_status gl_operator_destroy(gl_operator* op) {
+    free_op(op);
+    return GL_OK;
+}
+
+gl_status gl_operator_info(const gl_operator* op, int64_t* n, int64_t* nnz, gl_dtype* store_w,
+                           int32_t* lanes_per_row, size_t* device_bytes) {
+    if (!op) return fail(GL_E_INVALID_ARG, "operator is NULL");
+    if (n) *n = op->n;
+    if (nnz) *nnz = op->nnz;
+    if (store_w) *store_w = op->store_w;
+    if (lanes_per_row) *lanes_per_row = op->G;
+    if (device_bytes) *device_bytes = op->bytes;
+    return GL_OK;
+}
+
+gl_status gl_laplacian_apply(const gl_operator* op, int32_t K, gl_dtype dtype, const void* X, void* Y,
+                             void* stream) {
+    if (!op || !X || !Y) return fail(GL_E_INVALID_ARG, "operator, X and Y must not be NULL");
+    if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
+    if (!pair_ok(op->store_w, dtype)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
+    if (!aligned(X, 16) || !aligned(Y, 16)) return fail(GL_E_INVALID_ARG, "X and Y must be 16-byte aligned");
+    const size_t bytes = (size_t)op->n * K * dtype_size(dtype);
+    const char *x = (const char*)X, *y = (const char*)Y;
+    if (x < y + bytes && y < x + bytes) return fail(GL_E_INVALID_ARG, "X and Y overlap");
+    GL_HIP(launch_laplacian(dtype, K, row_launch(op), X, Y, (hipStream_t)stream), "laplacian launch");
+    return GL_OK;
+}
+
+gl_status gl_power_workspace_size(const gl_operator* op, size_t* bytes) {
+    if (!op || !bytes) return fail(GL_E_INVALID_ARG, "operator and bytes must not be NULL");
+    const gl::RowLaunch r = row_launch(op);
+    *bytes = 2 * align256((size_t)op->n * 4) + align256((size_t)2 * r.grid * 4) + 256;
+    return GL_OK;
+}
+
+gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0, void* ws, size_t ws_bytes,
+                           double* rayleigh, double* lambda_hat, void* stream) {
+    if (!op || !x0 || !ws || !rayleigh || !lambda_hat)
+        return fail(GL_E_INVALID_ARG, "operator, x0, workspace and outputs must not be NULL");
+    if (iters < 0) return fail(GL_E_INVALID_ARG, "iters must be >= 0");
+    if (op->store_w == GL_F64) return fail(GL_E_DTYPE, "the power method runs on F32/BF16/F16 weights");
+    if (!aligned(ws, 256)) return fail(GL_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    size_t need = 0;
+    gl_power_workspace_size(op, &need);
+    if (ws_bytes < need) return fail(GL_E_INVALID_ARG, "workspace too small");
+    hipStream_t s = (hipStream_t)stream;
+    const gl::RowLaunch r = row_launch(op);
+    char* base = (char*)ws;
+    float* buf[2] = {(float*)base, (float*)(base + align256((size_t)op->n * 4))};
+    float* partials = (float*)(base + 2 * align256((size_t)op->n * 4));
+    char* tail = (char*)partials + align256((size_t)2 * r.grid * 4);
+    float* scale = (float*)tail;
+    double* sums = (double*)(tail + 64);
+
+    auto pass = [&](const float* x, float* y, int mode, const float* sc) -> hipError_t {
+        const gl::RowGeom geo{r.n, r.rows_per_block, r.G, r.log2G, r.tiles, r.remap};
+        switch (op->store_w) {
+#define GL_POW(T)                                                                                   \
+    if (op->idx64) {                                                                                \
+        gl::PowerArgs<T, int64_t> a{(const int64_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, geo, mode}; \
+        hipLaunchKernelGGL((gl::power_kernel<T, int64_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
+    } else {                                                                                        \
+        gl::PowerArgs<T, int32_t> a{(const int32_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, geo, mode}; \
+        hipLaunchKernelGGL((gl::power_kernel<T, int32_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
+    }
+            case GL_F32: GL_POW(float) break;
+            case GL_BF16: GL_POW(gl::bf16) break;
+            case GL_F16: GL_POW(gl::f16) break;
+            default: return hipErrorInvalidValue;
+#undef GL_POW
+        }
+        return hipGetLastError();
+    };
+    auto finalize = [&](int scale_stat) -> hipError_t {
+        hipLaunchKernelGGL(gl::power_finalize_kernel, dim3(1), dim3(256), 0, s, partials, r.grid, scale_stat,
+                           scale, sums);
+        return hipGetLastError();
+    };
+    // s_0 = 1/|x0| from the mode-1 pass over x0
+    GL_HIP(pass(x0, nullptr, 1, nullptr), "power launch");
+    GL_HIP(finalize(1), "power finalize");
+    const float* x = x0;
+    for (int it = 0; it < iters; ++it) {
+        float* y = buf[it & 1];
+        GL_HIP(pass(x, y, 0, scale), "power launch");
+        GL_HIP(finalize(0), "power finalize");
+        x = y;
+    }
+    GL_HIP(pass(x, nullptr, 1, nullptr), "power launch");
+    GL_HIP(finalize(1), "power finalize");
+    double h[2] = {0, 0};
+    GL_HIP(hipMemcpyAsync(h, sums, sizeof(h), hipMemcpyDeviceToHost, s), "copy power sums");
+    GL_HIP(hipStreamSynchronize(s), "power method");
+    if (!(h[1] > 0) || !std::isfinite(h[0]) || !std::isfinite(h[1]))
+        return fail(GL_E_NONFINITE, "power method: x0 is zero or the iteration is not finite");
+    *rayleigh = h[0] / h[1];
+    *lambda_hat = std::fmin(2.0, 1.01 * *rayleigh);
+    return GL_OK;
+}
+
+gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype store_u, size_t* bytes) {
+    if (!op || !bytes) return fail(GL_E_INVALID_ARG, "operator and bytes must not be NULL");
+    if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
+    if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
+    const gl::RowLaunch r = row_launch(op);
+    const size_t field = align256((size_t)op->n * K * dtype_size(store_u));
+    const size_t acc = store_u == GL_F64 ? 8 : 4;
+    *bytes = 2 * field + align256((size_t)2 * K * r.grid * acc);
+    return GL_OK;
+}
+
+gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
+                   gl_dtype store_u, void* U, void* ws, size_t ws_bytes, double* stats, void* stream) {
+    if (!op || !labels || !U || !ws) return fail(GL_E_INVALID_ARG, "operator, labels, U and workspace must not be NULL");
+    gl_status st = check_params(params);
+    if (st != GL_OK) return st;
+    if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
+    if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
+    if (!aligned(U, 16)) return fail(GL_E_INVALID_ARG, "U must be 16-byte aligned");
+    if (!aligned(ws, 256)) return fail(GL_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (stats && !aligned(stats, 8)) return fail(GL_E_INVALID_ARG, "stats must be 8-byte aligned");
+    size_t need = 0;
+    gl_solve_workspace_size(op, K, store_u, &need);
+    if (ws_bytes < need) return fail(GL_E_INVALID_ARG, "workspace too small");
+    const gl_params& p = *params;
+    const int T = p.outer_steps, m = p.inner_sweeps;
+    hipStream_t s = (hipStream_t)stream;
+
+    const size_t field = align256((size_t)op->n * K * dtype_size(store_u));
+    char* bufs[3] = {(char*)U, (char*)ws, (char*)ws + field};
+    void* partials = (char*)ws + 2 * field;
+
+    gl::SweepLaunch L;
+    L.r = row_launch(op);
+    L.labels = labels;
+    L.partials = stats ? partials : nullptr;
+    const double g0 = precond_g(p.precond, 0.0, p), g1 = precond_g(p.precond, 1.0, p);
+    const bool inf_k = std::isinf(p.step_k);
+    const double coef[11] = {p.eps, p.c, p.eta, 1.0 / p.eps, 0.5 * p.eps, 0.25 / p.eps, 0.5 * p.eta,
+                             1.0 / g0, 1.0 / g1, inf_k ? 0.0 : 1.0, inf_k ? 1.0 : p.step_k};
+    std::memcpy(L.coef, coef, sizeof(coef));
+
+    const int64_t slen = gl_stats_length(K, T, m);
+    double* flag = stats ? stats + slen - 1 : nullptr;
+    double* res_base = stats ? stats + (int64_t)(T + 1) * K : nullptr;
+    if (stats) GL_HIP(fill_double(stats, slen, 0.0, s), "stats init");
+
+    auto finalize = [&](double* e_dst, double* r_dst) -> hipError_t {
+        if (!stats) return hipSuccess;
+        if (store_u == GL_F64) {
+            hipLaunchKernelGGL(gl::finalize_stats_kernel<double>, dim3(2 * K), dim3(256), 0, s,
+                               (const double*)partials, L.r.grid, K, e_dst, r_dst, flag);
+        } else {
+            hipLaunchKernelGGL(gl::finalize_stats_kernel<float>, dim3(2 * K), dim3(256), 0, s,
+                               (const float*)partials, L.r.grid, K, e_dst, r_dst, flag);
+        }
+        return hipGetLastError();
+    };
+
+    int cur = 0;  // buffer holding u^t
+    for (int t = 0; t < T; ++t) {
+        const int a = (cur + 1) % 3, b = (cur + 2) % 3;
+        int prev = cur;
+        for (int sw = 0; sw < m; ++sw) {
+            const int outb = (sw & 1) ? b : a;
+            L.ut = bufs[cur];
+            L.vin = bufs[prev];
+            L.vout = bufs[outb];
+            L.energy = (stats && sw == 0) ? 1 : 0;
+            GL_HIP(launch_sweep(store_u, K, L, s), "sweep launch");
+            GL_HIP(finalize(sw == 0 ? stats + (int64_t)t * K : nullptr,
+                            res_base ? res_base + ((int64_t)t * m + sw) * K : nullptr),
+                   "stats launch");
+            prev = outb;
+        }
+        cur = prev;
+    }
+    if (stats) {
+        // F(u^T): one more product, no update
+        L.ut = bufs[cur];
+        L.vin = bufs[cur];
+        L.vout = nullptr;
+        L.energy = 1;
+        GL_HIP(launch_sweep(store_u, K, L, s), "energy launch");
+        GL_HIP(finalize(stats + (int64_t)T * K, nullptr), "stats launch");
+    }
+    if (cur != 0)
+        GL_HIP(copy_bytes(bufs[cur], U, (size_t)op->n * K * dtype_size(store_u), s), "result copy");
+    return GL_OK;
+}
+
+gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
+                         gl_dtype store_u, const void* U, void* ws, size_t ws_bytes, int32_t reps, double* avg_ms,
+                         void* stream) {
+    if (!op || !labels || !U || !ws || !avg_ms) return fail(GL_E_INVALID_ARG, "NULL argument");
+    gl_status st = check_params(params);
+    if (st != GL_OK) return st;
+    if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
+    if (reps < 1) return fail(GL_E_INVALID_ARG, "reps must be >= 1");
+    if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
+    if (!aligned(U, 16) || !aligned(ws, 256)) return fail(GL_E_INVALID_ARG, "U / workspace misaligned");
+    size_t need = 0;
+    gl_solve_workspace_size(op, K, store_u, &need);
+    if (ws_bytes < need) return fail(GL_E_INVALID_ARG, "workspace too small");
+    const gl_params& p = *params;
+    hipStream_t s = (hipStream_t)stream;
+    const size_t field = align256((size_t)op->n * K * dtype_size(store_u));
+    char* P = (char*)ws;
+    char* Q = (char*)ws + field;
+    gl::SweepLaunch L;
+    L.r = row_launch(op);
+    L.labels = labels;
+    L.partials = (char*)ws + 2 * field;
+    L.energy = 0;
+    const double g0 = precond_g(p.precond, 0.0, p), g1 = precond_g(p.precond, 1.0, p);
+    const bool inf_k = std::isinf(p.step_k);
+    const double coef[11] = {p.eps, p.c, p.eta, 1.0 / p.eps, 0.5 * p.eps, 0.25 / p.eps, 0.5 * p.eta,
+                             1.0 / g0, 1.0 / g1, inf_k ? 0.0 : 1.0, inf_k ? 1.0 : p.step_k};
+    std::memcpy(L.coef, coef, sizeof(coef));
+    L.ut = U;
+    // seed P with u^t so every timed sweep gathers finite values
+    GL_HIP(copy_bytes(U, P, (size_t)op->n * K * dtype_size(store_u), s), "copy");
+    hipEvent_t e0, e1;
+    GL_HIP(hipEventCreate(&e0), "event");
+    GL_HIP(hipEventCreate(&e1), "event");
+    hipError_t err = hipEventRecord(e0, s);
+    for (int i = 0; i < reps && err == hipSuccess; ++i) {
+        L.vin = (i & 1) ? Q : P;
+        L.vout = (i & 1) ? P : Q;
+        err = launch_sweep(store_u, K, L, s);
+    }
+    if (err == hipSuccess) err = hipEventRecord(e1, s);
+    if (err == hipSuccess) err = hipEventSynchronize(e1);
+    float ms = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    GL_HIP(err, "timed sweeps");
+    *avg_ms = (double)ms / reps;
+    return GL_OK;
+}
+
+gl_status gl_assign_labels(int64_t n, int32_t K, gl_dtype dtype, const void* U, int32_t* out, void* stream) {
+    if (!U || !out || n < 0) return fail(GL_E_INVALID_ARG, "U and labels_out must not be NULL, n >= 0");
+    if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
+    if (n == 0) return GL_OK;
+    hipStream_t s = (hipStream_t)stream;
+    const dim3 grid((unsigned)((n + 255) / 256)), block(256);
+    switch (dtype) {
+        case GL_F64: hipLaunchKernelGGL(gl::labels_kernel<double>, grid, block, 0, s, n, K, (const double*)U, out); break;
+        case GL_F32: hipLaunchKernelGGL(gl::labels_kernel<float>, grid, block, 0, s, n, K, (const float*)U, out); break;
+        case GL_BF16: hipLaunchKernelGGL(gl::labels_kernel<gl::bf16>, grid, block, 0, s, n, K, (const gl::bf16*)U, out); break;
+        case GL_F16: hipLaunchKernelGGL(gl::labels_kernel<gl::f16>, grid, block, 0, s, n, K, (const gl::f16*)U, out); break;
+        default: return fail(GL_E_DTYPE, "unknown dtype");
+    }
+    GL_HIP(hipGetLastError(), "labels launch");
+    return GL_OK;
+}
+
+}  // extern "C"

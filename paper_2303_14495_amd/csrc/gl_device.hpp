@@ -1,0 +1,212 @@
+// Device-side building blocks of the gfx950 preconditioned-DCA library.
+//
+// The hot path is one kernel per sweep.  It forms Z = What V for the normalized
+// weights What = D^{-1/2} W D^{-1/2} (so L_s V = V - Z, Section 2.2), and fuses in
+// the same pass the right-hand side b = c u - (u^3 - u)/eps + eta Lambda y (Prop. 1),
+// the residual r = b - T v with T = eps L_s + eta Lambda + c I (Section 3), the
+// diagonal update v + r/g (Section 3.1) and the block partial sums of |r|^2 and of
+// the energy terms (Section 2.1).
+//
+// Work mapping (CDNA4, 64-lane wavefronts): a group of G lanes (G a power of two,
+// 4..64, chosen from the mean row length) owns one CSR row.  Lane q of the group
+// streams nonzeros q, q+G, q+2G, ... so one load instruction of the wavefront reads
+// 64/G consecutive rows' index and weight runs; each nonzero gathers the whole
+// K-wide row of V with one or a few vector loads.  The G partial sums are combined
+// by a butterfly of cross-lane swaps, which leaves the same bits in every lane of
+// the group; lane q then finishes columns q, q+G, ...  Every sum has a fixed order,
+// independent of K and of the launch, so results are bitwise reproducible.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace gl {
+
+// ----------------------------------------------------------------------------
+// storage types
+// ----------------------------------------------------------------------------
+struct bf16 {
+    uint16_t bits;
+};
+typedef _Float16 f16;
+
+template <typename T> struct acc_of { typedef float type; };
+template <> struct acc_of<double> { typedef double type; };
+
+template <typename A> __device__ __forceinline__ A cvt(double x) { return (A)x; }
+template <typename A> __device__ __forceinline__ A cvt(float x) { return (A)x; }
+template <typename A> __device__ __forceinline__ A cvt(f16 x) { return (A)(float)x; }
+template <typename A> __device__ __forceinline__ A cvt(bf16 x) {
+    return (A)__uint_as_float((uint32_t)x.bits << 16);
+}
+
+template <typename T> struct store_as;
+template <> struct store_as<double> {
+    static __device__ __forceinline__ double from(double x) { return x; }
+    static __device__ __forceinline__ double from(float x) { return (double)x; }
+};
+template <> struct store_as<float> {
+    static __device__ __forceinline__ float from(float x) { return x; }
+    static __device__ __forceinline__ float from(double x) { return (float)x; }
+};
+// Single rounding (to nearest even) from double.  Normal results: round the
+// double's significand to the target width on the bit pattern; the rounded
+// value is then exact in float and in the target.  Subnormal results: round to
+// the fixed quantum with rint (round-half-even in the default mode).
+__device__ __forceinline__ float round_double_to_width(double x, int drop_bits, double min_normal,
+                                                       double quantum_inv, double quantum) {
+    const double ax = fabs(x);
+    if (!(ax >= min_normal)) {
+        if (x != x) return __builtin_nanf("");
+        return (float)(rint(x * quantum_inv) * quantum);
+    }
+    uint64_t d = (uint64_t)__double_as_longlong(x);
+    const uint64_t half = (1ull << (drop_bits - 1)) - 1ull;
+    d += half + ((d >> drop_bits) & 1ull);
+    d &= ~((1ull << drop_bits) - 1ull);
+    return (float)__longlong_as_double((long long)d);
+}
+
+template <> struct store_as<f16> {
+    // round to nearest even (the default rounding of the conversion)
+    static __device__ __forceinline__ f16 from(float x) { return (f16)x; }
+    static __device__ __forceinline__ f16 from(double x) {
+        if (fabs(x) > 65504.0) return (f16)(float)x;
+        // 10 stored significand bits: drop 42 of the double's 52
+        return (f16)round_double_to_width(x, 42, 6.103515625e-05, 16777216.0, 5.9604644775390625e-08);
+    }
+};
+template <> struct store_as<bf16> {
+    // round to nearest even on the bit pattern; NaN stays NaN
+    static __device__ __forceinline__ bf16 from(float x) {
+        uint32_t u = __float_as_uint(x);
+        if ((u & 0x7fffffffu) > 0x7f800000u) return bf16{(uint16_t)((u >> 16) | 0x40u)};
+        u += 0x7fffu + ((u >> 16) & 1u);
+        return bf16{(uint16_t)(u >> 16)};
+    }
+    static __device__ __forceinline__ bf16 from(double x) {
+        if (fabs(x) > 3.0e38) return from((float)x);
+        // 7 stored significand bits: drop 45 of the double's 52; quantum 2^-133 below 2^-126
+        const float f = round_double_to_width(x, 45, 1.1754943508222875e-38,
+                                              1.0889035741470030e+40, 9.1835496157991212e-41);
+        return bf16{(uint16_t)(__float_as_uint(f) >> 16)};
+    }
+};
+
+// ----------------------------------------------------------------------------
+// vector gather of one K-wide row of V
+// ----------------------------------------------------------------------------
+typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
+typedef uint32_t u32x2 __attribute__((ext_vector_type(2)));
+
+template <int B> struct chunk_t;
+template <> struct chunk_t<16> { typedef u32x4 type; };
+template <> struct chunk_t<8> { typedef u32x2 type; };
+template <> struct chunk_t<4> { typedef uint32_t type; };
+template <> struct chunk_t<2> { typedef uint16_t type; };
+
+template <int K, typename T, typename A>
+__device__ __forceinline__ void load_row(const T* __restrict__ p, A (&out)[K]) {
+    constexpr int RB = K * (int)sizeof(T);
+    constexpr int CB = (RB % 16 == 0) ? 16 : (RB % 8 == 0) ? 8 : (RB % 4 == 0) ? 4 : 2;
+    typedef typename chunk_t<CB>::type C;
+    C buf[RB / CB];
+    const C* src = reinterpret_cast<const C*>(p);
+#pragma unroll
+    for (int c = 0; c < RB / CB; ++c) buf[c] = src[c];
+    T vals[K];
+    __builtin_memcpy(vals, buf, RB);
+#pragma unroll
+    for (int k = 0; k < K; ++k) out[k] = cvt<A>(vals[k]);
+}
+
+// runtime-index read of a register array without spilling it to scratch
+template <int K, typename A>
+__device__ __forceinline__ A pick(const A (&z)[K], int k) {
+    A r = z[0];
+#pragma unroll
+    for (int i = 1; i < K; ++i) r = (k == i) ? z[i] : r;
+    return r;
+}
+
+// Hardware dispatch hands consecutive workgroup ids round-robin to the 8 XCDs.
+// Give every XCD a contiguous range of logical blocks so that the rows it works
+// on at any moment, and the V rows they gather, stay in that XCD's own L2.
+__device__ __forceinline__ int64_t xcd_remap(int64_t b, int64_t nb) {
+    const int64_t q = nb >> 3, r = nb & 7;
+    const int64_t x = b & 7, i = b >> 3;
+    return (x < r) ? x * (q + 1) + i : r * (q + 1) + (x - r) * q + i;
+}
+
+// z = sum_j what_ij V[j, :] for `row`, completed in every lane of its G-lane group.
+// Rows >= n contribute zeros but still take part in the cross-lane swaps.
+template <int K, typename TW, typename TU, typename OffT, typename A>
+__device__ __forceinline__ void row_gather(const OffT* __restrict__ rp, const int32_t* __restrict__ col,
+                                           const TW* __restrict__ w, const TU* __restrict__ V,
+                                           int64_t row, int64_t n, int q, int G, A (&z)[K]) {
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = (A)0;
+    if (row < n) {
+        const OffT beg = rp[row], end = rp[row + 1];
+        OffT p = beg + (OffT)q;
+        for (; p + (OffT)G < end; p += (OffT)(2 * G)) {
+            const int32_t j0 = col[p], j1 = col[p + G];
+            const A w0 = cvt<A>(w[p]), w1 = cvt<A>(w[p + G]);
+            A v0[K], v1[K];
+            load_row<K>(V + (int64_t)j0 * K, v0);
+            load_row<K>(V + (int64_t)j1 * K, v1);
+#pragma unroll
+            for (int k = 0; k < K; ++k) z[k] += w0 * v0[k];
+#pragma unroll
+            for (int k = 0; k < K; ++k) z[k] += w1 * v1[k];
+        }
+        if (p < end) {
+            const int32_t j0 = col[p];
+            const A w0 = cvt<A>(w[p]);
+            A v0[K];
+            load_row<K>(V + (int64_t)j0 * K, v0);
+#pragma unroll
+            for (int k = 0; k < K; ++k) z[k] += w0 * v0[k];
+        }
+    }
+    for (int off = G >> 1; off > 0; off >>= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) z[k] += __shfl_xor(z[k], off, 64);
+    }
+}
+
+// Sum the per-lane column partials of a 256-thread block.  Lane q of every group
+// holds columns q, q+G, ...; after the cross-group swaps lanes 0..G-1 of each
+// wavefront hold the wavefront's sums, which four LDS slots combine in wavefront
+// order.  Thread s < 2K writes statistic s (energies then residuals) of this block.
+template <int K, int CPL, typename A>
+__device__ __forceinline__ void block_stats(A (&e)[CPL], A (&r)[CPL], int G, A* __restrict__ partials,
+                                            int64_t nb, int64_t b) {
+    __shared__ A sh[4][2][K];
+    for (int off = G; off < 64; off <<= 1) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            e[c] += __shfl_xor(e[c], off, 64);
+            r[c] += __shfl_xor(r[c], off, 64);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane < G) {
+#pragma unroll
+        for (int c = 0; c < CPL; ++c) {
+            const int k = lane + c * G;
+            if (k < K) {
+                sh[wave][0][k] = e[c];
+                sh[wave][1][k] = r[c];
+            }
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * K) {
+        const int kind = threadIdx.x / K, k = threadIdx.x - kind * K;
+        const A s = ((sh[0][kind][k] + sh[1][kind][k]) + sh[2][kind][k]) + sh[3][kind][k];
+        partials[(int64_t)threadIdx.x * nb + b] = s;
+    }
+}
+
+}  // namespace gl

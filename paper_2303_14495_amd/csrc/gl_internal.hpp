@@ -1,0 +1,49 @@
+// Host-side interfaces between the C ABI and the per-storage-type kernel units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/gl_dca.h"
+
+namespace gl {
+
+// Untyped description of one row-kernel launch; the unit compiled for the
+// field's storage type casts the pointers and picks the K instantiation.
+struct RowLaunch {
+    const void* rp;      // int32 or int64 row offsets
+    const int32_t* col;
+    const void* w;       // normalized weights in the operator's storage type
+    gl_dtype wdt;
+    bool idx64;
+    int64_t n;
+    int64_t grid;
+    int64_t rows_per_block;
+    int32_t G, log2G, tiles, remap;
+};
+
+struct SweepLaunch {
+    RowLaunch r;
+    const void* ut;
+    const void* vin;
+    void* vout;
+    const int32_t* labels;
+    void* partials;
+    int32_t energy;
+    // eps, c, eta, 1/eps, eps/2, 1/(4 eps), eta/2, 1/g0, 1/g1, alpha, kappa
+    double coef[11];
+};
+
+// Each returns hipSuccess or the launch error; hipErrorInvalidValue when the
+// (weight type, K) combination is not compiled for this field type.
+hipError_t launch_sweep_f64(int K, const SweepLaunch& L, hipStream_t s);
+hipError_t launch_sweep_f32(int K, const SweepLaunch& L, hipStream_t s);
+hipError_t launch_sweep_bf16(int K, const SweepLaunch& L, hipStream_t s);
+hipError_t launch_sweep_f16(int K, const SweepLaunch& L, hipStream_t s);
+
+hipError_t launch_laplacian_f64(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s);
+hipError_t launch_laplacian_f32(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s);
+hipError_t launch_laplacian_bf16(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s);
+hipError_t launch_laplacian_f16(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s);
+
+}  // namespace gl

@@ -1,0 +1,345 @@
+// Kernels of the gfx950 preconditioned-DCA library and their launch helpers.
+#pragma once
+
+#include "gl_device.hpp"
+
+namespace gl {
+
+constexpr int kBlock = 256;  // 4 wavefronts of 64 lanes
+
+// Per-launch geometry shared by the row kernels: block b (after the XCD remap)
+// owns rows [b * rows_per_block, (b + 1) * rows_per_block), processed as `tiles`
+// passes of 256 / G rows.
+struct RowGeom {
+    int64_t n;
+    int64_t rows_per_block;
+    int32_t G;
+    int32_t log2G;
+    int32_t tiles;
+    int32_t remap;
+};
+
+template <typename A> struct SweepCoef {
+    A eps, c, eta;          // model parameters
+    A inv_eps;              // 1 / eps
+    A half_eps, quarter_inv_eps, half_eta;  // energy prefactors
+    A ginv0, ginv1;         // 1 / g for unlabelled (Lambda = 0) and labelled rows
+    A alpha, kappa;         // r = alpha (u^t - v) + kappa (b - T v)
+};
+
+template <typename TW, typename TU, typename OffT> struct SweepArgs {
+    typedef typename acc_of<TU>::type A;
+    const OffT* rp;
+    const int32_t* col;
+    const TW* w;
+    const TU* ut;      // u^t, read on the own row for b
+    const TU* vin;     // v^s, gathered
+    TU* vout;          // v^{s+1}; nullptr for the energy-only pass
+    const int32_t* labels;
+    A* partials;       // [2K][grid] block partial sums, or nullptr
+    RowGeom g;
+    int32_t energy;    // also accumulate the energy terms (vin == ut)
+    SweepCoef<A> k;
+};
+
+// One sweep (or the energy-only pass) for K columns.
+template <int K, typename TW, typename TU, typename OffT>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a) {
+    typedef typename acc_of<TU>::type A;
+    constexpr int CPL = (K + 3) / 4;  // columns per lane (G >= 4)
+    const int G = a.g.G;
+    const int q = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x >> a.g.log2G;
+    const int rows_per_tile = kBlock >> a.g.log2G;
+    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t row0 = b * a.g.rows_per_block;
+    A e_acc[CPL], r_acc[CPL];
+#pragma unroll
+    for (int c = 0; c < CPL; ++c) e_acc[c] = r_acc[c] = (A)0;
+
+    for (int t = 0; t < a.g.tiles; ++t) {
+        const int64_t row = row0 + (int64_t)t * rows_per_tile + grp;
+        A z[K];
+        row_gather<K>(a.rp, a.col, a.w, a.vin, row, a.g.n, q, G, z);
+        if (row < a.g.n) {
+            const int32_t lab = a.labels[row];
+            const A lam = lab >= 0 ? (A)1 : (A)0;
+            const A ginv = lab >= 0 ? a.k.ginv1 : a.k.ginv0;
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int k = q + c * G;
+                if (k < K) {
+                    const A zk = pick<K>(z, k);
+                    const int64_t at = row * K + k;
+                    const A u = cvt<A>(a.ut[at]);
+                    const A v = cvt<A>(a.vin[at]);
+                    const A y = lab < 0 ? (A)0
+                              : (K == 1 ? (lab == 1 ? (A)1 : (A)-1) : (lab == k ? (A)1 : (A)-1));
+                    const A rhs = a.k.c * u - (u * u * u - u) * a.k.inv_eps + a.k.eta * lam * y;
+                    const A tv = a.k.eps * (v - zk) + (a.k.eta * lam + a.k.c) * v;
+                    const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
+                    if (a.vout) a.vout[at] = store_as<TU>::from(v + r * ginv);
+                    r_acc[c] += r * r;
+                    if (a.energy) {
+                        const A u2m1 = u * u - (A)1, dy = u - y;
+                        e_acc[c] += a.k.half_eps * (u * u - u * zk) + a.k.quarter_inv_eps * u2m1 * u2m1 +
+                                    a.k.half_eta * lam * dy * dy;
+                    }
+                }
+            }
+        }
+    }
+    if (a.partials) block_stats<K, CPL>(e_acc, r_acc, G, a.partials, (int64_t)gridDim.x, b);
+}
+
+// Y = X - What X  (L_s X, Section 2.2)
+template <typename TW, typename TU, typename OffT> struct LapArgs {
+    const OffT* rp;
+    const int32_t* col;
+    const TW* w;
+    const TU* x;
+    TU* y;
+    RowGeom g;
+};
+
+template <int K, typename TW, typename TU, typename OffT>
+__global__ __launch_bounds__(kBlock) void laplacian_kernel(LapArgs<TW, TU, OffT> a) {
+    typedef typename acc_of<TU>::type A;
+    constexpr int CPL = (K + 3) / 4;
+    const int G = a.g.G;
+    const int q = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x >> a.g.log2G;
+    const int rows_per_tile = kBlock >> a.g.log2G;
+    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t row0 = b * a.g.rows_per_block;
+    for (int t = 0; t < a.g.tiles; ++t) {
+        const int64_t row = row0 + (int64_t)t * rows_per_tile + grp;
+        A z[K];
+        row_gather<K>(a.rp, a.col, a.w, a.x, row, a.g.n, q, G, z);
+        if (row < a.g.n) {
+#pragma unroll
+            for (int c = 0; c < CPL; ++c) {
+                const int k = q + c * G;
+                if (k < K) {
+                    const int64_t at = row * K + k;
+                    a.y[at] = store_as<TU>::from(cvt<A>(a.x[at]) - pick<K>(z, k));
+                }
+            }
+        }
+    }
+}
+
+// Power-method pass on float vectors.  mode 0: y = s (x - What x) with s = *scale,
+// partial[0] = sum y^2.  mode 1: partial[0] = sum x (x - What x), partial[1] = sum x^2.
+template <typename TW, typename OffT> struct PowerArgs {
+    const OffT* rp;
+    const int32_t* col;
+    const TW* w;
+    const float* x;
+    float* y;
+    const float* scale;
+    float* partials;  // [2][grid]
+    RowGeom g;
+    int32_t mode;
+};
+
+template <typename TW, typename OffT>
+__global__ __launch_bounds__(kBlock) void power_kernel(PowerArgs<TW, OffT> a) {
+    const int G = a.g.G;
+    const int q = threadIdx.x & (G - 1);
+    const int grp = threadIdx.x >> a.g.log2G;
+    const int rows_per_tile = kBlock >> a.g.log2G;
+    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    const int64_t row0 = b * a.g.rows_per_block;
+    const float s = a.mode == 0 ? *a.scale : 1.0f;
+    float p0 = 0.f, p1 = 0.f;
+    for (int t = 0; t < a.g.tiles; ++t) {
+        const int64_t row = row0 + (int64_t)t * rows_per_tile + grp;
+        float z[1];
+        row_gather<1>(a.rp, a.col, a.w, a.x, row, a.g.n, q, G, z);
+        if (row < a.g.n && q == 0) {
+            const float xv = a.x[row];
+            const float lx = xv - z[0];
+            if (a.mode == 0) {
+                const float yv = s * lx;
+                a.y[row] = yv;
+                p0 += yv * yv;
+            } else {
+                p0 += xv * lx;
+                p1 += xv * xv;
+            }
+        }
+    }
+    float e[1] = {p0}, r[1] = {p1};
+    block_stats<1, 1>(e, r, G, a.partials, (int64_t)gridDim.x, b);
+}
+
+// Fixed-order double reduction of one statistic per block: block s sums
+// partials[s * nb .. s * nb + nb).
+template <typename P>
+__device__ __forceinline__ double block_sum(const P* __restrict__ src, int64_t nb) {
+    __shared__ double sh[kBlock / 64];
+    double acc = 0.0;
+    for (int64_t i = threadIdx.x; i < nb; i += kBlock) acc += (double)src[i];
+    for (int off = 32; off > 0; off >>= 1) acc += __shfl_xor(acc, off, 64);
+    if ((threadIdx.x & 63) == 0) sh[threadIdx.x >> 6] = acc;
+    __syncthreads();
+    return ((sh[0] + sh[1]) + sh[2]) + sh[3];
+}
+
+// Solve statistics: block s < K -> energy column s, block K + k -> |r|^2 of column k.
+template <typename P>
+__global__ __launch_bounds__(kBlock) void finalize_stats_kernel(const P* partials, int64_t nb, int32_t K,
+                                                                 double* energy_dst, double* res_dst,
+                                                                 double* flag) {
+    const int s = blockIdx.x;
+    double* dst = s < K ? energy_dst : res_dst;
+    if (dst == nullptr) return;  // uniform per block
+    const double v = block_sum(partials + (int64_t)s * nb, nb);
+    if (threadIdx.x == 0) {
+        dst[s < K ? s : s - K] = v;
+        if (!(fabs(v) <= 1.7976931348623157e308)) *flag = 1.0;
+    }
+}
+
+// Power method: scale_out = 1 / sqrt(sum partial[scale_stat]); sums_out (optional)
+// gets both sums in double.
+static __global__ __launch_bounds__(kBlock) void power_finalize_kernel(const float* partials, int64_t nb,
+                                                                int32_t scale_stat, float* scale_out,
+                                                                double* sums_out) {
+    const double s0 = block_sum(partials, nb);
+    __syncthreads();
+    const double s1 = block_sum(partials + nb, nb);
+    if (threadIdx.x == 0) {
+        if (scale_out) *scale_out = (float)(1.0 / sqrt(scale_stat ? s1 : s0));
+        if (sums_out) {
+            sums_out[0] = s0;
+            sums_out[1] = s1;
+        }
+    }
+}
+
+static __global__ void fill_double_kernel(double* p, int64_t n, double v) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+static __global__ void copy_bytes_kernel(const u32x4* __restrict__ src, u32x4* __restrict__ dst, int64_t n16,
+                                  const uint8_t* __restrict__ src_tail, uint8_t* __restrict__ dst_tail,
+                                  int32_t tail) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n16) dst[i] = src[i];
+    if (i < tail) dst_tail[i] = src_tail[i];
+}
+
+template <typename TU>
+__global__ void labels_kernel(int64_t n, int32_t K, const TU* __restrict__ U, int32_t* __restrict__ out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    typedef typename acc_of<TU>::type A;
+    if (K == 1) {
+        out[i] = cvt<A>(U[i]) >= (A)0 ? 1 : 0;
+        return;
+    }
+    A best = cvt<A>(U[i * K]);
+    int32_t arg = 0;
+    for (int k = 1; k < K; ++k) {
+        const A v = cvt<A>(U[i * K + k]);
+        if (v > best) {
+            best = v;
+            arg = k;
+        }
+    }
+    out[i] = arg;
+}
+
+// ---------------------------------------------------------------------------
+// operator construction (once per graph)
+// ---------------------------------------------------------------------------
+enum : int32_t {
+    BAD_ROWPTR = 1,
+    BAD_COL_RANGE = 2,
+    BAD_COL_ORDER = 4,
+    BAD_SELF_LOOP = 8,
+    BAD_WEIGHT = 16,
+    BAD_ASYMMETRIC = 32,
+    BAD_DEGREE = 64
+};
+
+template <typename TIN>
+__global__ void validate_kernel(int64_t n, int64_t nnz, const int64_t* __restrict__ rp,
+                                const int32_t* __restrict__ col, const TIN* __restrict__ w,
+                                int32_t* flags, unsigned long long* first_bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    int32_t f = 0;
+    const int64_t beg = rp[i], end = rp[i + 1];
+    if (beg < 0 || end < beg || end > nnz) {
+        f |= BAD_ROWPTR;
+    } else {
+        int64_t prev = -1;
+        for (int64_t p = beg; p < end; ++p) {
+            const int64_t j = col[p];
+            if (j < 0 || j >= n) {
+                f |= BAD_COL_RANGE;
+                break;
+            }
+            if (j <= prev) f |= BAD_COL_ORDER;
+            prev = j;
+            if (j == i) f |= BAD_SELF_LOOP;
+            const double wv = (double)w[p];
+            if (!(wv > 0.0) || !(wv <= 1.7976931348623157e308)) f |= BAD_WEIGHT;
+            // symmetry: find i in row j by binary search and compare the weight bits
+            const int64_t jb = rp[j], je = rp[j + 1];
+            if (jb < 0 || je < jb || je > nnz) {
+                f |= BAD_ROWPTR;
+                continue;
+            }
+            int64_t lo = jb, hi = je;
+            while (lo < hi) {
+                const int64_t mid = (lo + hi) >> 1;
+                if (col[mid] < i) lo = mid + 1; else hi = mid;
+            }
+            if (lo >= je || col[lo] != i || !(w[lo] == w[p])) f |= BAD_ASYMMETRIC;
+        }
+    }
+    if (f) {
+        atomicOr(flags, f);
+        atomicMin(first_bad, (unsigned long long)i);
+    }
+}
+
+template <typename TIN>
+__global__ void degree_kernel(int64_t n, const int64_t* __restrict__ rp, const TIN* __restrict__ w,
+                              double* __restrict__ d, int32_t* flags, unsigned long long* first_bad) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += (double)w[p];
+    d[i] = s;
+    if (!(s > 0.0) || !(s <= 1.7976931348623157e308)) {
+        atomicOr(flags, (int32_t)BAD_DEGREE);
+        atomicMin(first_bad, (unsigned long long)i);
+    }
+}
+
+// what_ij = w_ij / sqrt(d_i d_j) in double, rounded once to TOUT; the index
+// arrays are copied (row offsets narrowed to OffT) in the same pass.
+template <typename TIN, typename TOUT, typename OffT>
+__global__ void normalize_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
+                                 const TIN* __restrict__ w, const double* __restrict__ d,
+                                 OffT* __restrict__ rp_out, int32_t* __restrict__ col_out,
+                                 TOUT* __restrict__ w_out) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i > n) return;
+    rp_out[i] = (OffT)rp[i];
+    if (i == n) return;
+    const double di = d[i];
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
+        const int32_t j = col[p];
+        col_out[p] = j;
+        w_out[p] = store_as<TOUT>::from((double)w[p] / sqrt(di * d[j]));
+    }
+}
+
+}  // namespace gl

@@ -1,0 +1,113 @@
+// Typed launch of the sweep and Laplacian kernels for one field storage type TU.
+// Included by one translation unit per TU so the K x weight-type x index-width
+// instantiations compile in parallel.
+#pragma once
+
+#include "gl_internal.hpp"
+#include "gl_kernels.hpp"
+
+namespace gl {
+
+template <typename TW, typename TU, typename OffT>
+static SweepArgs<TW, TU, OffT> make_sweep_args(const SweepLaunch& L) {
+    typedef typename acc_of<TU>::type A;
+    SweepArgs<TW, TU, OffT> a;
+    a.rp = static_cast<const OffT*>(L.r.rp);
+    a.col = L.r.col;
+    a.w = static_cast<const TW*>(L.r.w);
+    a.ut = static_cast<const TU*>(L.ut);
+    a.vin = static_cast<const TU*>(L.vin);
+    a.vout = static_cast<TU*>(L.vout);
+    a.labels = L.labels;
+    a.partials = static_cast<A*>(L.partials);
+    a.g = RowGeom{L.r.n, L.r.rows_per_block, L.r.G, L.r.log2G, L.r.tiles, L.r.remap};
+    a.energy = L.energy;
+    a.k.eps = (A)L.coef[0];
+    a.k.c = (A)L.coef[1];
+    a.k.eta = (A)L.coef[2];
+    a.k.inv_eps = (A)L.coef[3];
+    a.k.half_eps = (A)L.coef[4];
+    a.k.quarter_inv_eps = (A)L.coef[5];
+    a.k.half_eta = (A)L.coef[6];
+    a.k.ginv0 = (A)L.coef[7];
+    a.k.ginv1 = (A)L.coef[8];
+    a.k.alpha = (A)L.coef[9];
+    a.k.kappa = (A)L.coef[10];
+    return a;
+}
+
+#define GL_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
+
+template <typename TW, typename TU, typename OffT>
+static hipError_t sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
+    const SweepArgs<TW, TU, OffT> a = make_sweep_args<TW, TU, OffT>(L);
+    const dim3 grid((unsigned)L.r.grid), block(kBlock);
+    switch (K) {
+#define GL_CASE(KK)                                                           \
+    case KK:                                                                  \
+        hipLaunchKernelGGL((sweep_kernel<KK, TW, TU, OffT>), grid, block, 0, s, a); \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TW, typename TU, typename OffT>
+static hipError_t laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
+    LapArgs<TW, TU, OffT> a;
+    a.rp = static_cast<const OffT*>(r.rp);
+    a.col = r.col;
+    a.w = static_cast<const TW*>(r.w);
+    a.x = static_cast<const TU*>(x);
+    a.y = static_cast<TU*>(y);
+    a.g = RowGeom{r.n, r.rows_per_block, r.G, r.log2G, r.tiles, r.remap};
+    const dim3 grid((unsigned)r.grid), block(kBlock);
+    switch (K) {
+#define GL_CASE(KK)                                                                  \
+    case KK:                                                                         \
+        hipLaunchKernelGGL((laplacian_kernel<KK, TW, TU, OffT>), grid, block, 0, s, a); \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+// Weight types paired with a reduced-precision or float field.
+template <typename TU>
+static hipError_t sweep_lowp(int K, const SweepLaunch& L, hipStream_t s) {
+    switch (L.r.wdt) {
+        case GL_F32:
+            return L.r.idx64 ? sweep_k<float, TU, int64_t>(K, L, s) : sweep_k<float, TU, int32_t>(K, L, s);
+        case GL_BF16:
+            return L.r.idx64 ? sweep_k<bf16, TU, int64_t>(K, L, s) : sweep_k<bf16, TU, int32_t>(K, L, s);
+        case GL_F16:
+            return L.r.idx64 ? sweep_k<f16, TU, int64_t>(K, L, s) : sweep_k<f16, TU, int32_t>(K, L, s);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+template <typename TU>
+static hipError_t laplacian_lowp(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
+    switch (r.wdt) {
+        case GL_F32:
+            return r.idx64 ? laplacian_k<float, TU, int64_t>(K, r, x, y, s)
+                           : laplacian_k<float, TU, int32_t>(K, r, x, y, s);
+        case GL_BF16:
+            return r.idx64 ? laplacian_k<bf16, TU, int64_t>(K, r, x, y, s)
+                           : laplacian_k<bf16, TU, int32_t>(K, r, x, y, s);
+        case GL_F16:
+            return r.idx64 ? laplacian_k<f16, TU, int64_t>(K, r, x, y, s)
+                           : laplacian_k<f16, TU, int32_t>(K, r, x, y, s);
+        default:
+            return hipErrorInvalidValue;
+    }
+}
+
+}  // namespace gl

@@ -1,0 +1,259 @@
+"""ctypes binding of ``libgl_dca.so`` (declared in include/gl_dca.h).
+
+Argument marshalling only: every step of the solve runs in the library's HIP
+kernels.  torch supplies device memory (tensors) and streams.  If the shared
+library has not been built this module raises on first use; there is no
+fallback path.
+"""
+
+from __future__ import annotations
+
+import ctypes
+import math
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libgl_dca.so")
+
+DTYPES = {"f64": 0, "f32": 1, "bf16": 2, "f16": 3}
+TORCH_DTYPES = {"f64": torch.float64, "f32": torch.float32, "bf16": torch.bfloat16,
+                "f16": torch.float16}
+DTYPE_OF_TORCH = {v: k for k, v in TORCH_DTYPES.items()}
+PRECONDS = {"damped_jacobi": 0, "perturbed_jacobi": 1, "richardson": 2}
+STATUS = {0: "GL_OK", 1: "GL_E_INVALID_ARG", 2: "GL_E_BAD_GRAPH", 3: "GL_E_DTYPE",
+          4: "GL_E_NOMEM", 5: "GL_E_BUDGET", 6: "GL_E_NONFINITE", 7: "GL_E_HIP",
+          8: "GL_E_QUEUE_FULL", 9: "GL_E_NOT_READY", 10: "GL_E_CANCELLED"}
+
+
+class GLError(RuntimeError):
+    def __init__(self, status: int, message: str):
+        super().__init__(f"{STATUS.get(status, status)}: {message}")
+        self.status = status
+        self.message = message
+
+
+class _Graph(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+                ("weight_dtype", ctypes.c_int32)]
+
+
+class _Params(ctypes.Structure):
+    _fields_ = [("eps", ctypes.c_double), ("c", ctypes.c_double), ("eta", ctypes.c_double),
+                ("delta0", ctypes.c_double), ("lambda_max", ctypes.c_double),
+                ("step_k", ctypes.c_double), ("precond", ctypes.c_int32),
+                ("outer_steps", ctypes.c_int32), ("inner_sweeps", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+_lib = None
+
+# symbol -> (restype, argtypes)
+_P, _I32, _I64, _SZ, _D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_size_t,
+                          ctypes.c_double)
+SIGNATURES = {
+    "gl_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "gl_operator_destroy": (ctypes.c_int, [_P]),
+    "gl_operator_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "gl_laplacian_apply": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P]),
+    "gl_power_workspace_size": (ctypes.c_int, [_P, _P]),
+    "gl_power_max_eig": (ctypes.c_int, [_P, _I32, _P, _P, _SZ, _P, _P, _P]),
+    "gl_solve_workspace_size": (ctypes.c_int, [_P, _I32, _I32, _P]),
+    "gl_stats_length": (ctypes.c_int64, [_I32, _I32, _I32]),
+    "gl_solve": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _P, _P, _SZ, _P, _P]),
+    "gl_assign_labels": (ctypes.c_int, [_I64, _I32, _I32, _P, _P, _P]),
+    "gl_params_validate": (ctypes.c_int, [_P]),
+    "gl_time_sweeps": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _P, _P, _SZ, _I32, _P, _P]),
+    "gl_last_error": (ctypes.c_char_p, []),
+    "gl_version": (ctypes.c_char_p, []),
+}
+
+
+def load_library(path: str = LIB_PATH):
+    """Load the HIP library; raise if it has not been built."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError(f"{path} is missing: build the HIP library first "
+                           "(python -c 'import __graft_entry__ as g; g.build()')")
+    lib = ctypes.CDLL(path)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def _check(status: int):
+    if status != 0:
+        msg = load_library().gl_last_error()
+        raise GLError(status, msg.decode() if msg else "")
+
+
+def _stream_handle(stream=None):
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return ctypes.c_void_p(s.cuda_stream)
+
+
+def _ptr(t: torch.Tensor):
+    return ctypes.c_void_p(t.data_ptr())
+
+
+def stats_length(K: int, outer: int, sweeps: int) -> int:
+    return int(load_library().gl_stats_length(K, outer, sweeps))
+
+
+def split_stats(stats: torch.Tensor, K: int, outer: int, sweeps: int):
+    """(energies [T+1, K], residual_sq [T, m, K], nonfinite flag) from a stats vector."""
+    e = stats[: (outer + 1) * K].view(outer + 1, K)
+    r = stats[(outer + 1) * K: (outer + 1) * K + outer * sweeps * K].view(outer, sweeps, K)
+    return e, r, float(stats[-1])
+
+
+class Operator:
+    """Normalized graph operator What = D^{-1/2} W D^{-1/2} held on the GPU.
+
+    row_ptr (int64 [n+1]), col (int32 [nnz]) and weight (float64 or float32
+    [nnz]) are CUDA tensors of a symmetric graph without self-loops.
+    """
+
+    def __init__(self, row_ptr, col, weight, store_w: str = "f32", stream=None):
+        lib = load_library()
+        if not (row_ptr.is_cuda and col.is_cuda and weight.is_cuda):
+            raise ValueError("graph tensors must live on the GPU")
+        if row_ptr.dtype != torch.int64 or col.dtype != torch.int32:
+            raise ValueError("row_ptr must be int64 and col int32")
+        if weight.dtype not in (torch.float64, torch.float32):
+            raise ValueError("weight must be float64 or float32")
+        self.row_ptr, self.col, self.weight = (row_ptr.contiguous(), col.contiguous(),
+                                               weight.contiguous())
+        self.n = int(row_ptr.numel() - 1)
+        self.nnz = int(col.numel())
+        self.store_w = store_w
+        self.device = row_ptr.device
+        g = _Graph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
+                   self.weight.data_ptr(), DTYPES[DTYPE_OF_TORCH[weight.dtype]])
+        handle = ctypes.c_void_p()
+        self._h = None
+        _check(lib.gl_operator_create(ctypes.byref(g), DTYPES[store_w], _stream_handle(stream),
+                                      ctypes.byref(handle)))
+        self._h = handle
+        self._ws = {}
+        # the library holds its own copies; drop the references
+        self.row_ptr = self.col = self.weight = None
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().gl_operator_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @property
+    def handle(self):
+        return self._h
+
+    def info(self) -> dict:
+        n, nnz, sw, lanes, by = (ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int32(),
+                                 ctypes.c_int32(), ctypes.c_size_t())
+        _check(load_library().gl_operator_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
+                                               ctypes.byref(sw), ctypes.byref(lanes),
+                                               ctypes.byref(by)))
+        return {"n": n.value, "nnz": nnz.value, "lanes_per_row": lanes.value,
+                "device_bytes": by.value}
+
+    def _workspace(self, key, nbytes):
+        ws = self._ws.get(key)
+        if ws is None or ws.numel() < nbytes:
+            ws = torch.empty(max(nbytes, 256), dtype=torch.uint8, device=self.device)
+            self._ws[key] = ws
+        return ws
+
+    def laplacian_apply(self, X: torch.Tensor, stream=None) -> torch.Tensor:
+        X2 = X if X.dim() == 2 else X.view(-1, 1)
+        X2 = X2.contiguous()
+        Y = torch.empty_like(X2)
+        _check(load_library().gl_laplacian_apply(self._h, X2.shape[1],
+                                                 DTYPES[DTYPE_OF_TORCH[X2.dtype]], _ptr(X2),
+                                                 _ptr(Y), _stream_handle(stream)))
+        return Y.view_as(X)
+
+    def power_max_eig(self, x0: torch.Tensor, iters: int = 150, stream=None):
+        lib = load_library()
+        nb = ctypes.c_size_t()
+        _check(lib.gl_power_workspace_size(self._h, ctypes.byref(nb)))
+        ws = self._workspace("power", nb.value)
+        x0 = x0.to(torch.float32).contiguous()
+        rq, lam = ctypes.c_double(), ctypes.c_double()
+        _check(lib.gl_power_max_eig(self._h, iters, _ptr(x0), _ptr(ws), ws.numel(),
+                                    ctypes.byref(rq), ctypes.byref(lam), _stream_handle(stream)))
+        return rq.value, lam.value
+
+    def workspace_bytes(self, K: int, store_u: str) -> int:
+        nb = ctypes.c_size_t()
+        _check(load_library().gl_solve_workspace_size(self._h, K, DTYPES[store_u],
+                                                      ctypes.byref(nb)))
+        return nb.value
+
+    def solve(self, labels: torch.Tensor, U: torch.Tensor, *, eps, c, eta, precond, outer,
+              sweeps, delta0=1e-6, lambda_max=2.0, step_k=math.inf, stats=True, stream=None,
+              stats_out: torch.Tensor | None = None):
+        """Run the preconditioned DCA in place on U (n x K, f64/f32/bf16/f16).
+
+        Returns the stats vector (float64 on the GPU) or None.
+        """
+        lib = load_library()
+        if U.dim() == 1:
+            raise ValueError("U must be n x K")
+        if not U.is_contiguous() or labels.dtype != torch.int32 or not labels.is_contiguous():
+            raise ValueError("U must be contiguous and labels contiguous int32")
+        K = U.shape[1]
+        store_u = DTYPE_OF_TORCH[U.dtype]
+        ws = self._workspace(("solve", K, store_u), self.workspace_bytes(K, store_u))
+        p = _Params(eps, c, eta, delta0, lambda_max, step_k, PRECONDS[precond], outer, sweeps, 0)
+        st = None
+        if stats:
+            st = stats_out if stats_out is not None else torch.empty(
+                stats_length(K, outer, sweeps), dtype=torch.float64, device=U.device)
+        _check(lib.gl_solve(self._h, ctypes.byref(p), K, _ptr(labels), DTYPES[store_u], _ptr(U),
+                            _ptr(ws), ws.numel(), _ptr(st) if st is not None else None,
+                            _stream_handle(stream)))
+        return st
+
+
+def time_sweeps(op: Operator, labels: torch.Tensor, U: torch.Tensor, *, eps, c, eta, precond,
+                delta0=1e-6, lambda_max=2.0, step_k=math.inf, reps=20, stream=None) -> float:
+    """Mean duration (ms) of the sweep kernel, timed with HIP events on the stream."""
+    lib = load_library()
+    K = U.shape[1]
+    store_u = DTYPE_OF_TORCH[U.dtype]
+    ws = op._workspace(("solve", K, store_u), op.workspace_bytes(K, store_u))
+    p = _Params(eps, c, eta, delta0, lambda_max, step_k, PRECONDS[precond], 1, 1, 0)
+    out = ctypes.c_double()
+    _check(lib.gl_time_sweeps(op.handle, ctypes.byref(p), K, _ptr(labels), DTYPES[store_u],
+                              _ptr(U), _ptr(ws), ws.numel(), reps, ctypes.byref(out),
+                              _stream_handle(stream)))
+    return out.value
+
+
+def assign_labels(U: torch.Tensor, stream=None) -> torch.Tensor:
+    """Class per node (K = 1: u >= 0 -> 1; K >= 2: argmax, ties to the lowest)."""
+    U2 = U if U.dim() == 2 else U.view(-1, 1)
+    U2 = U2.contiguous()
+    out = torch.empty(U2.shape[0], dtype=torch.int32, device=U.device)
+    _check(load_library().gl_assign_labels(U2.shape[0], U2.shape[1],
+                                           DTYPES[DTYPE_OF_TORCH[U2.dtype]], _ptr(U2), _ptr(out),
+                                           _stream_handle(stream)))
+    return out
+
+
+def version() -> str:
+    return load_library().gl_version().decode()

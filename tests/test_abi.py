@@ -1,0 +1,91 @@
+"""Host-side checks of the C ABI: the library loads without a GPU, exports
+every entry point the header declares, and rejects bad arguments before any
+launch."""
+
+import ctypes
+import math
+import os
+import re
+
+import pytest
+
+import paper_2303_14495_amd as gl
+from paper_2303_14495_amd import gl as glmod
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _declared_functions():
+    names = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if not fn.endswith(".h"):
+            continue
+        txt = open(os.path.join(ROOT, "include", fn)).read()
+        txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+        names |= set(re.findall(r"\b(gl_[a-z0-9_]+)\s*\(", txt))
+    return names
+
+
+def test_library_exports_every_declared_symbol():
+    lib = gl.load_library()
+    declared = _declared_functions()
+    assert "gl_solve" in declared and "gl_operator_create" in declared
+    for name in sorted(declared):
+        assert hasattr(lib, name), f"{name} declared in include/ but not exported"
+
+
+def test_binding_covers_declared_symbols():
+    declared = _declared_functions()
+    missing = declared - set(glmod.SIGNATURES)
+    assert not missing, missing
+
+
+def test_version_and_stats_length():
+    assert "gfx950" in gl.version()
+    K, T, m = 3, 5, 4
+    assert gl.stats_length(K, T, m) == (T + 1) * K + T * m * K + 1
+    assert gl.stats_length(0, T, m) == 0
+
+
+def _params(**kw):
+    base = dict(eps=1.0, c=3.0, eta=10.0, delta0=1e-6, lambda_max=1.5, step_k=math.inf,
+                precond=0, outer_steps=2, inner_sweeps=2, reserved=0)
+    base.update(kw)
+    return glmod._Params(**base)
+
+
+@pytest.mark.parametrize("bad", [
+    dict(eps=0.0), dict(eps=-1.0), dict(eps=math.nan), dict(c=0.0), dict(eta=-1.0),
+    dict(delta0=-1e-3), dict(precond=7), dict(precond=2, lambda_max=0.0),
+    dict(precond=2, lambda_max=2.5), dict(step_k=0.0), dict(step_k=-math.inf),
+    dict(step_k=math.nan), dict(outer_steps=-1), dict(inner_sweeps=0), dict(reserved=1),
+])
+def test_params_rejected(bad):
+    lib = gl.load_library()
+    p = _params(**bad)
+    assert lib.gl_params_validate(ctypes.byref(p)) == 1
+    assert lib.gl_last_error()
+
+
+def test_params_accepted():
+    lib = gl.load_library()
+    for kw in [dict(), dict(precond=2, lambda_max=2.0), dict(step_k=0.5), dict(eta=0.0),
+               dict(outer_steps=0)]:
+        p = _params(**kw)
+        assert lib.gl_params_validate(ctypes.byref(p)) == 0
+
+
+def test_null_arguments_rejected():
+    lib = gl.load_library()
+    assert lib.gl_operator_create(None, 1, None, None) == 1
+    assert lib.gl_solve(None, None, 1, None, 1, None, None, 0, None, None) == 1
+    assert lib.gl_laplacian_apply(None, 1, 1, None, None, None) == 1
+    assert lib.gl_assign_labels(10, 1, 1, None, None, None) == 1
+    assert lib.gl_params_validate(None) == 1
+    assert lib.gl_operator_destroy(None) == 0
+
+
+def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
+    monkeypatch.setattr(glmod, "_lib", None)
+    with pytest.raises(RuntimeError, match="missing"):
+        glmod.load_library(str(tmp_path / "nope.so"))
