@@ -32,12 +32,12 @@ METRIC = "Laplacian-sweep HBM GB/s + DCA solves/s (FP32 vs BF16); served p50/p99
 DSIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 
 
-def sweep_bytes(n, nnz, K, store_w, store_u, idx64=False):
-    """Algorithmic bytes of one sweep: index + weight streams, row offsets,
-    the compulsory read of the gathered field, the own-row read of u^t, the
-    write of the new field, and the labels."""
-    rp = 8 if idx64 else 4
-    return (nnz * (4 + DSIZE[store_w]) + rp * (n + 1) + 3 * n * K * DSIZE[store_u] + 4 * n)
+def sweep_bytes(info, n, K, store_u):
+    """Algorithmic bytes of one sweep: the operator's index, weight, row-offset
+    and order streams as stored (padding included), the compulsory read of the
+    gathered field, the own-row read of u^t, the write of the new field, and
+    the labels."""
+    return info["stream_bytes"] + 3 * n * K * DSIZE[store_u] + 4 * n
 
 
 def parse():
@@ -49,6 +49,8 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=40)
+    ap.add_argument("--calib-copy", action="store_true",
+                    help="finish with a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
 
 
@@ -100,6 +102,7 @@ def main():
     p = make_problem(args.workload, device=dev)
     log(f"  {p.name}: n={p.n} nnz={p.graph.nnz} K={p.K} ({time.perf_counter() - t:.1f} s)")
     g = p.graph
+    order = torch.from_numpy(p.order).to(dev) if p.order is not None else None
     labels = torch.from_numpy(p.labels).to(dev)
     x0 = torch.from_numpy(np.random.default_rng(10_000 + p.seed).uniform(-1, 1, p.n)).to(
         dev, torch.float32)
@@ -107,7 +110,7 @@ def main():
     def run_variant(store_w, store_u, steps, warmup):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        op = gl.Operator(g.row_ptr, g.col, g.weight, store_w=store_w)
+        op = gl.Operator(g.row_ptr, g.col, g.weight, store_w=store_w, order=order)
         torch.cuda.synchronize()
         t_create = time.perf_counter() - t0
         lam = 2.0
@@ -129,7 +132,7 @@ def main():
                                   precond=p.precond, delta0=p.delta0, lambda_max=lam,
                                   step_k=p.step_k, reps=args.sweep_reps)
         info = op.info()
-        B = sweep_bytes(p.n, g.nnz, p.K, store_w, store_u)
+        B = sweep_bytes(info, p.n, p.K, store_u)
         res = {
             "solves_per_s": steps / wall,
             "ms_per_solve": wall / steps * 1e3,
@@ -140,7 +143,10 @@ def main():
             "operator_create_ms": t_create * 1e3,
             "power_method_ms": t_power * 1e3,
             "lambda_hat": lam,
-            "lanes_per_row": info["lanes_per_row"],
+            "layout": info["layout"],
+            "stored_entries": info["stored_entries"],
+            "halo_max": info["halo_max"],
+            "halo_total": info["halo_total"],
         }
         labels_out = gl.assign_labels(U_first).cpu().numpy()
         op.close()
@@ -155,7 +161,8 @@ def main():
         fp32, lab32, _ = run_variant("f32", "f32", args.steps, args.warmup)
         fp32["label_agreement_with_main"] = float(np.mean(lab32 == lab_main))
         fp32 = {k: fp32[k] for k in ("solves_per_s", "ms_per_solve", "sweep_kernel_ms",
-                                     "sweep_bytes", "sweep_gbps", "label_agreement_with_main")}
+                                     "sweep_bytes", "sweep_gbps", "label_agreement_with_main",
+                                     "power_method_ms", "layout")}
     acc = float(np.mean(lab_main == p.truth))
 
     cpu = None
@@ -198,6 +205,8 @@ def main():
         "sweep_kernel_ms": main_res["sweep_kernel_ms"],
         "per_graph_setup_ms": {"operator_create": main_res["operator_create_ms"],
                                "power_method_150": main_res["power_method_ms"]},
+        "layout": {k: main_res[k] for k in ("layout", "stored_entries", "halo_max",
+                                            "halo_total")},
         "accuracy_vs_ground_truth": acc,
         "fp32": fp32,
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
@@ -206,6 +215,11 @@ def main():
         "cpu_baseline": cpu,
     }
     print(json.dumps(out), flush=True)
+    if args.calib_copy:
+        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

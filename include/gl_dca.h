@@ -64,12 +64,30 @@ typedef enum gl_precond {
     GL_PC_RICHARDSON = 2
 } gl_precond;
 
+/* Storage layout of the operator (chosen once, at creation, from the graph
+ * alone, so every K and every solve sums each row in the same order).
+ *   AUTO    tile layout when `order` is given and every block of 256 rows
+ *           references few enough distinct columns, else direct
+ *   DIRECT  CSR rows (in `order`, if given) with 32-bit columns; gathers from
+ *           global memory
+ *   TILE    rows in `order` cut into blocks of 256; each block's distinct
+ *           columns (its halo) are staged in LDS and every entry stores a
+ *           16-bit index into the halo; rows padded to 4-entry multiples.
+ *           Fails with GL_E_INVALID_ARG when a halo exceeds the limit. */
+typedef enum gl_layout { GL_LAYOUT_AUTO = 0, GL_LAYOUT_DIRECT = 1, GL_LAYOUT_TILE = 2 } gl_layout;
+
 /* Weighted undirected graph in CSR form (Section 2.2), device memory.
  *   row_ptr  int64 [n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
  *   col_idx  int32 [nnz], strictly increasing within a row, in [0, n),
  *            no self-loops (w_ii = 0, so diag(L_s) = 1)
  *   weight   [nnz] of weight_dtype (GL_F64 or GL_F32), finite, > 0,
  *            symmetric: w_ij == w_ji bit for bit with the same pattern
+ *   order    int32 [n] or NULL: a permutation of 0..n-1 giving the order in
+ *            which rows are processed (position p handles node order[p]).
+ *            It changes nothing in the result but the rounding order of the
+ *            sums; a locality-preserving order (e.g. the Z-order of an image's
+ *            pixel grid) lets the tile layout keep each block's gathers in LDS.
+ *   layout   gl_layout request.
  * Every degree d_i = sum_j w_ij must be > 0. */
 typedef struct gl_graph {
     int64_t n;
@@ -78,6 +96,8 @@ typedef struct gl_graph {
     const int32_t *col_idx;
     const void *weight;
     gl_dtype weight_dtype;
+    const int32_t *order;
+    int32_t layout;
 } gl_graph;
 
 /* Solver parameters (Section 3 and Section 3.1).
@@ -109,8 +129,9 @@ typedef struct gl_operator gl_operator;
  * (see gl_graph), computes d_i = sum_j w_ij in F64 and stores
  * what_ij = w_ij / sqrt(d_i d_j) rounded to `store_w` (GL_F64, GL_F32,
  * GL_BF16 or GL_F16) in library-owned device memory, with its own copy of the
- * index arrays; the caller may free `graph`'s arrays after return.
- * Synchronises `stream`.  Errors: GL_E_INVALID_ARG, GL_E_BAD_GRAPH (message
+ * index arrays; the caller may free `graph`'s arrays after return.  With an
+ * order or a tile request the index layout is built on the host (the CSR
+ * pattern is copied back once).  Synchronises `stream`.  Errors: GL_E_INVALID_ARG, GL_E_BAD_GRAPH (message
  * names the first defect), GL_E_DTYPE, GL_E_NOMEM, GL_E_HIP. */
 gl_status gl_operator_create(const gl_graph *graph, gl_dtype store_w, void *stream,
                              gl_operator **out);
@@ -120,9 +141,15 @@ gl_status gl_operator_create(const gl_graph *graph, gl_dtype store_w, void *stre
 gl_status gl_operator_destroy(gl_operator *op);
 
 /* Host: number of nodes, stored nonzeros, weight storage type, lanes per
- * row chosen for the sparse product, and device bytes held. */
+ * row of the sparse product, and device bytes held.  Any pointer may be NULL. */
 gl_status gl_operator_info(const gl_operator *op, int64_t *n, int64_t *nnz,
                            gl_dtype *store_w, int32_t *lanes_per_row, size_t *device_bytes);
+
+/* Host: layout chosen (GL_LAYOUT_DIRECT or GL_LAYOUT_TILE), entries stored
+ * (with padding), largest halo and total halo entries (tile only), and the
+ * bytes of index/weight/order arrays one sweep streams.  Any pointer may be NULL. */
+gl_status gl_operator_layout(const gl_operator *op, int32_t *layout, int64_t *stored_entries,
+                             int32_t *halo_max, int64_t *halo_total, int64_t *stream_bytes);
 
 /* Y = L_s X = X - D^{-1/2} W D^{-1/2} X (Section 2.2) for device X, Y of
  * n x K elements of `dtype` (1 <= K <= 16); X and Y must not overlap. */

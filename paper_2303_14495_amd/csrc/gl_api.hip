@@ -7,16 +7,27 @@
 #include <cstring>
 #include <string>
 
+#include <vector>
+
 #include "gl_internal.hpp"
 #include "gl_kernels.hpp"
+#include "gl_layout.hpp"
+#include "gl_tile.hpp"
 
 struct gl_operator {
-    int64_t n = 0, nnz = 0;
+    int64_t n = 0, nnz = 0, stored = 0;
     int device = 0;
     gl_dtype store_w = GL_F32;
+    int32_t layout = gl::LAYOUT_DIRECT;
     bool idx64 = false;
-    void* rp = nullptr;
-    int32_t* col = nullptr;
+    int32_t* order = nullptr;   // node of each position (nullptr = natural order)
+    void* rp = nullptr;         // direct: int32/int64 offsets; tile: int32 padded offsets
+    int32_t* col = nullptr;     // direct only
+    uint16_t* lcol = nullptr;   // tile only
+    int32_t* halo = nullptr;    // tile only
+    int32_t* hp = nullptr;      // tile only
+    int32_t hmax = 0;
+    int64_t halo_total = 0, nblocks = 0;
     void* w = nullptr;
     double* degree = nullptr;
     int32_t G = 16, log2G = 4, tiles = 4, remap = 1;
@@ -58,13 +69,27 @@ int env_int(const char* name, int dflt) {
 }
 
 gl::RowLaunch row_launch(const gl_operator* op) {
-    gl::RowLaunch r;
-    r.rp = op->rp;
-    r.col = op->col;
+    gl::RowLaunch r = {};
+    r.layout = op->layout;
     r.w = op->w;
     r.wdt = op->store_w;
-    r.idx64 = op->idx64;
+    r.order = op->order;
     r.n = op->n;
+    if (op->layout == gl::LAYOUT_TILE) {
+        r.trp = (const int32_t*)op->rp;
+        r.lcol = op->lcol;
+        r.halo = op->halo;
+        r.hp = op->hp;
+        r.hmax = op->hmax;
+        r.grid = op->nblocks;
+        r.rows_per_block = gl::kTileRows;
+        r.idx64 = false;
+        r.G = gl::kTileG;
+        return r;
+    }
+    r.rp = op->rp;
+    r.col = op->col;
+    r.idx64 = op->idx64;
     r.G = op->G;
     r.log2G = op->log2G;
     r.tiles = op->tiles;
@@ -177,11 +202,42 @@ void launch_normalize_out(gl_operator* op, const gl_graph* g, hipStream_t s) {
 
 void free_op(gl_operator* op) {
     if (!op) return;
+    (void)hipFree(op->order);
     (void)hipFree(op->rp);
     (void)hipFree(op->col);
+    (void)hipFree(op->lcol);
+    (void)hipFree(op->halo);
+    (void)hipFree(op->hp);
     (void)hipFree(op->w);
     (void)hipFree(op->degree);
     delete op;
+}
+
+template <typename TIN, typename TOUT>
+void launch_fill(gl_operator* op, const gl_graph* g, const int32_t* src, hipStream_t s) {
+    const unsigned grid = (unsigned)((op->n + 255) / 256);
+    hipLaunchKernelGGL((gl::fill_layout_kernel<TIN, TOUT>), dim3(grid), dim3(256), 0, s, op->n,
+                       (const int32_t*)op->rp, src, op->order, g->col_idx, static_cast<const TIN*>(g->weight),
+                       op->degree, static_cast<TOUT*>(op->w), op->col);
+}
+
+template <typename TIN>
+void launch_fill_out(gl_operator* op, const gl_graph* g, const int32_t* src, hipStream_t s) {
+    switch (op->store_w) {
+        case GL_F64: launch_fill<TIN, double>(op, g, src, s); break;
+        case GL_F32: launch_fill<TIN, float>(op, g, src, s); break;
+        case GL_BF16: launch_fill<TIN, gl::bf16>(op, g, src, s); break;
+        case GL_F16: launch_fill<TIN, gl::f16>(op, g, src, s); break;
+    }
+}
+
+template <typename T>
+hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s) {
+    const size_t bytes = v.size() * sizeof(T);
+    hipError_t e = hipMalloc((void**)dst, bytes ? bytes : sizeof(T));
+    if (e != hipSuccess) return e;
+    if (bytes) e = hipMemcpyAsync(*dst, v.data(), bytes, hipMemcpyHostToDevice, s);
+    return e;
 }
 
 std::string bad_graph_message(int32_t flags, unsigned long long row) {
@@ -218,18 +274,23 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     if (g->weight_dtype != GL_F64 && g->weight_dtype != GL_F32)
         return fail(GL_E_DTYPE, "input weights must be GL_F64 or GL_F32");
     if (dtype_size(store_w) == 0) return fail(GL_E_DTYPE, "unknown store_w");
+    if (g->layout < GL_LAYOUT_AUTO || g->layout > GL_LAYOUT_TILE) return fail(GL_E_INVALID_ARG, "unknown layout");
+    const bool host_layout = g->order != nullptr || g->layout == GL_LAYOUT_TILE;
+    if (host_layout && g->nnz > (int64_t)INT32_MAX)
+        return fail(GL_E_INVALID_ARG, "an order or the tile layout needs nnz < 2^31");
     hipStream_t s = (hipStream_t)stream;
 
     gl_operator* op = new gl_operator();
     op->n = g->n;
     op->nnz = g->nnz;
+    op->stored = g->nnz;
     op->store_w = store_w;
     op->idx64 = g->nnz > (int64_t)INT32_MAX;
     if (hipGetDevice(&op->device) != hipSuccess) {
         delete op;
         return fail(GL_E_HIP, "hipGetDevice failed");
     }
-    // geometry of the row kernels: G lanes per row from the mean row length
+    // geometry of the direct row kernels: G lanes per row from the mean row length
     const double avg = (double)g->nnz / (double)g->n;
     int G = 4;
     while (G < 64 && 2.0 * G <= avg) G *= 2;
@@ -242,19 +303,12 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     if (op->tiles < 1 || op->tiles > 64) op->tiles = 4;
     op->remap = env_int("GL_XCD_REMAP", 1) ? 1 : 0;
 
-    const size_t rp_bytes = (size_t)(g->n + 1) * (op->idx64 ? 8 : 4);
-    const size_t col_bytes = (size_t)g->nnz * 4;
-    const size_t w_bytes = (size_t)g->nnz * dtype_size(store_w);
-    const size_t d_bytes = (size_t)g->n * 8;
-    void* scratch = nullptr;  // [int32 flags][pad][u64 first_bad][int64 rp0, rpn]
-    if (hipMalloc(&op->rp, rp_bytes) != hipSuccess || hipMalloc((void**)&op->col, col_bytes) != hipSuccess ||
-        hipMalloc(&op->w, w_bytes) != hipSuccess || hipMalloc((void**)&op->degree, d_bytes) != hipSuccess ||
-        hipMalloc(&scratch, 64) != hipSuccess) {
+    void* scratch = nullptr;  // [int32 flags][pad][u64 first_bad]
+    if (hipMalloc((void**)&op->degree, (size_t)g->n * 8) != hipSuccess || hipMalloc(&scratch, 64) != hipSuccess) {
         (void)hipFree(scratch);
         free_op(op);
         return fail(GL_E_NOMEM, "device allocation for the operator failed");
     }
-    op->bytes = rp_bytes + col_bytes + w_bytes + d_bytes;
     int32_t* d_flags = (int32_t*)scratch;
     unsigned long long* d_first = (unsigned long long*)((char*)scratch + 8);
     struct {
@@ -262,9 +316,11 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         unsigned long long first;
     } init = {0, 0, ~0ull};
     int64_t ends[2] = {-1, -1};
+    int32_t* d_src = nullptr;
     auto cleanup_fail = [&](gl_status st, const std::string& m) {
         (void)hipStreamSynchronize(s);
         (void)hipFree(scratch);
+        (void)hipFree(d_src);
         free_op(op);
         return fail(st, m);
     };
@@ -302,10 +358,79 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         return cleanup_fail(GL_E_HIP, "degree computation failed");
     if (init.flags) return cleanup_fail(GL_E_BAD_GRAPH, bad_graph_message(init.flags, init.first));
 
-    if (g->weight_dtype == GL_F64) launch_normalize_out<double>(op, g, s);
-    else launch_normalize_out<float>(op, g, s);
+    const size_t sw = dtype_size(store_w);
+    if (!host_layout) {
+        // direct layout in natural order, built on the device
+        const size_t rp_bytes = (size_t)(g->n + 1) * (op->idx64 ? 8 : 4);
+        if (hipMalloc(&op->rp, rp_bytes) != hipSuccess || hipMalloc((void**)&op->col, (size_t)g->nnz * 4) != hipSuccess ||
+            hipMalloc(&op->w, (size_t)g->nnz * sw) != hipSuccess)
+            return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
+        op->bytes = rp_bytes + (size_t)g->nnz * (4 + sw) + (size_t)g->n * 8;
+        if (g->weight_dtype == GL_F64) launch_normalize_out<double>(op, g, s);
+        else launch_normalize_out<float>(op, g, s);
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return cleanup_fail(GL_E_HIP, "weight normalization failed");
+        (void)hipFree(scratch);
+        *out = op;
+        return GL_OK;
+    }
+
+    // processing order and/or tile layout: index layout built on the host
+    std::vector<int64_t> h_rp(g->n + 1);
+    std::vector<int32_t> h_col(g->nnz), h_order;
+    if (hipMemcpy(h_rp.data(), g->row_ptr, h_rp.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+        hipMemcpy(h_col.data(), g->col_idx, h_col.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+        return cleanup_fail(GL_E_HIP, "copying the CSR pattern to the host failed");
+    if (g->order) {
+        h_order.resize(g->n);
+        if (hipMemcpy(h_order.data(), g->order, h_order.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
+            return cleanup_fail(GL_E_HIP, "copying the order to the host failed");
+        std::vector<char> seen(g->n, 0);
+        for (int64_t p = 0; p < g->n; ++p) {
+            const int32_t i = h_order[p];
+            if (i < 0 || i >= g->n || seen[i])
+                return cleanup_fail(GL_E_INVALID_ARG, "order is not a permutation of 0..n-1 (position " +
+                                                          std::to_string(p) + ")");
+            seen[i] = 1;
+        }
+    }
+    gl::HostLayout L;
+    std::string err;
+    const int32_t halo_limit = store_w == GL_F64 ? 480 : gl::kTileHaloMax;
+    if (!gl::build_layout(g->n, h_rp.data(), h_col.data(), g->order ? h_order.data() : nullptr,
+                          g->layout != GL_LAYOUT_DIRECT, g->layout == GL_LAYOUT_TILE, halo_limit, L, err))
+        return cleanup_fail(GL_E_INVALID_ARG, err);
+    h_col.clear();
+    h_col.shrink_to_fit();
+    op->layout = L.layout == 1 ? gl::LAYOUT_TILE : gl::LAYOUT_DIRECT;
+    op->idx64 = false;
+    op->stored = (int64_t)L.src.size();
+    hipError_t e = hipSuccess;
+    if (g->order) e = upload(&op->order, h_order, s);
+    if (e == hipSuccess) e = upload((int32_t**)&op->rp, L.rp, s);
+    if (e == hipSuccess) e = upload(&d_src, L.src, s);
+    if (e == hipSuccess && op->layout == gl::LAYOUT_TILE) {
+        e = upload(&op->lcol, L.lcol, s);
+        if (e == hipSuccess) e = upload(&op->halo, L.halo, s);
+        if (e == hipSuccess) e = upload(&op->hp, L.hp, s);
+        op->hmax = L.hmax;
+        op->halo_total = (int64_t)L.halo.size();
+        op->nblocks = (int64_t)L.hp.size() - 1;
+    }
+    if (e == hipSuccess && op->layout == gl::LAYOUT_DIRECT)
+        e = hipMalloc((void**)&op->col, (size_t)op->stored * 4 + 4);
+    if (e == hipSuccess) e = hipMalloc(&op->w, (size_t)op->stored * sw + 16);
+    if (e != hipSuccess) return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
+    op->bytes = (size_t)(g->n + 1) * 4 + (size_t)op->stored * sw + (size_t)g->n * 8 +
+                (g->order ? (size_t)g->n * 4 : 0) +
+                (op->layout == gl::LAYOUT_TILE ? (size_t)op->stored * 2 + (size_t)op->halo_total * 4 +
+                                                     (size_t)(op->nblocks + 1) * 4
+                                               : (size_t)op->stored * 4);
+    if (g->weight_dtype == GL_F64) launch_fill_out<double>(op, g, d_src, s);
+    else launch_fill_out<float>(op, g, d_src, s);
     if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
         return cleanup_fail(GL_E_HIP, "weight normalization failed");
+    (void)hipFree(d_src);
     (void)hipFree(scratch);
     *out = op;
     return GL_OK;
@@ -326,6 +451,22 @@ gl_status gl_operator_info(const gl_operator* op, int64_t* n, int64_t* nnz, gl_d
     if (store_w) *store_w = op->store_w;
     if (lanes_per_row) *lanes_per_row = op->G;
     if (device_bytes) *device_bytes = op->bytes;
+    return GL_OK;
+}
+
+gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* stored, int32_t* halo_max,
+                             int64_t* halo_total, int64_t* stream_bytes) {
+    if (!op) return fail(GL_E_INVALID_ARG, "operator is NULL");
+    const bool tile = op->layout == gl::LAYOUT_TILE;
+    if (layout) *layout = tile ? GL_LAYOUT_TILE : GL_LAYOUT_DIRECT;
+    if (stored) *stored = op->stored;
+    if (halo_max) *halo_max = tile ? op->hmax : 0;
+    if (halo_total) *halo_total = tile ? op->halo_total : 0;
+    if (stream_bytes) {
+        const int64_t rp = (op->n + 1) * (op->idx64 ? 8 : 4);
+        const int64_t idx = tile ? op->stored * 2 + op->halo_total * 4 + (op->nblocks + 1) * 4 : op->stored * 4;
+        *stream_bytes = rp + idx + op->stored * (int64_t)dtype_size(op->store_w) + (op->order ? op->n * 4 : 0);
+    }
     return GL_OK;
 }
 
@@ -369,14 +510,44 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
     double* sums = (double*)(tail + 64);
 
     auto pass = [&](const float* x, float* y, int mode, const float* sc) -> hipError_t {
+        if (op->layout == gl::LAYOUT_TILE) {
+            gl::TilePowerArgs a;
+            a.op.rp = (const int32_t*)op->rp;
+            a.op.lcol = op->lcol;
+            a.op.w = op->w;
+            a.op.halo = op->halo;
+            a.op.hp = op->hp;
+            a.op.order = op->order;
+            a.op.n = op->n;
+            a.x = x;
+            a.y = y;
+            a.scale = sc;
+            a.partials = partials;
+            a.mode = mode;
+            const size_t lds = (size_t)op->hmax * 4;
+            switch (op->store_w) {
+                case GL_F32:
+                    hipLaunchKernelGGL(gl::tile_power_kernel<float>, dim3((unsigned)r.grid), dim3(256), lds, s, a);
+                    break;
+                case GL_BF16:
+                    hipLaunchKernelGGL(gl::tile_power_kernel<gl::bf16>, dim3((unsigned)r.grid), dim3(256), lds, s, a);
+                    break;
+                case GL_F16:
+                    hipLaunchKernelGGL(gl::tile_power_kernel<gl::f16>, dim3((unsigned)r.grid), dim3(256), lds, s, a);
+                    break;
+                default:
+                    return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
         const gl::RowGeom geo{r.n, r.rows_per_block, r.G, r.log2G, r.tiles, r.remap};
         switch (op->store_w) {
 #define GL_POW(T)                                                                                   \
     if (op->idx64) {                                                                                \
-        gl::PowerArgs<T, int64_t> a{(const int64_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, geo, mode}; \
+        gl::PowerArgs<T, int64_t> a{(const int64_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, op->order, geo, mode}; \
         hipLaunchKernelGGL((gl::power_kernel<T, int64_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
     } else {                                                                                        \
-        gl::PowerArgs<T, int32_t> a{(const int32_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, geo, mode}; \
+        gl::PowerArgs<T, int32_t> a{(const int32_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, op->order, geo, mode}; \
         hipLaunchKernelGGL((gl::power_kernel<T, int32_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
     }
             case GL_F32: GL_POW(float) break;

@@ -8,18 +8,29 @@
 
 namespace gl {
 
+enum Layout : int32_t { LAYOUT_DIRECT = 0, LAYOUT_TILE = 1 };
+
 // Untyped description of one row-kernel launch; the unit compiled for the
 // field's storage type casts the pointers and picks the K instantiation.
 struct RowLaunch {
-    const void* rp;      // int32 or int64 row offsets
-    const int32_t* col;
-    const void* w;       // normalized weights in the operator's storage type
+    int32_t layout;
+    const void* w;        // normalized weights in the operator's storage type
     gl_dtype wdt;
-    bool idx64;
+    const int32_t* order; // node of each position, or nullptr
     int64_t n;
     int64_t grid;
+    // direct layout
+    const void* rp;       // int32 or int64 row offsets
+    const int32_t* col;
+    bool idx64;
     int64_t rows_per_block;
     int32_t G, log2G, tiles, remap;
+    // tile layout
+    const int32_t* trp;
+    const uint16_t* lcol;
+    const int32_t* halo;
+    const int32_t* hp;
+    int32_t hmax;
 };
 
 struct SweepLaunch {

@@ -36,6 +36,7 @@ template <typename TW, typename TU, typename OffT> struct SweepArgs {
     const TU* vin;     // v^s, gathered
     TU* vout;          // v^{s+1}; nullptr for the energy-only pass
     const int32_t* labels;
+    const int32_t* order;  // node of each row position, or nullptr (identity)
     A* partials;       // [2K][grid] block partial sums, or nullptr
     RowGeom g;
     int32_t energy;    // also accumulate the energy terms (vin == ut)
@@ -62,7 +63,8 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a
         A z[K];
         row_gather<K>(a.rp, a.col, a.w, a.vin, row, a.g.n, q, G, z);
         if (row < a.g.n) {
-            const int32_t lab = a.labels[row];
+            const int64_t node = a.order ? (int64_t)a.order[row] : row;
+            const int32_t lab = a.labels[node];
             const A lam = lab >= 0 ? (A)1 : (A)0;
             const A ginv = lab >= 0 ? a.k.ginv1 : a.k.ginv0;
 #pragma unroll
@@ -70,7 +72,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a
                 const int k = q + c * G;
                 if (k < K) {
                     const A zk = pick<K>(z, k);
-                    const int64_t at = row * K + k;
+                    const int64_t at = node * K + k;
                     const A u = cvt<A>(a.ut[at]);
                     const A v = cvt<A>(a.vin[at]);
                     const A y = lab < 0 ? (A)0
@@ -99,6 +101,7 @@ template <typename TW, typename TU, typename OffT> struct LapArgs {
     const TW* w;
     const TU* x;
     TU* y;
+    const int32_t* order;
     RowGeom g;
 };
 
@@ -117,11 +120,12 @@ __global__ __launch_bounds__(kBlock) void laplacian_kernel(LapArgs<TW, TU, OffT>
         A z[K];
         row_gather<K>(a.rp, a.col, a.w, a.x, row, a.g.n, q, G, z);
         if (row < a.g.n) {
+            const int64_t node = a.order ? (int64_t)a.order[row] : row;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int k = q + c * G;
                 if (k < K) {
-                    const int64_t at = row * K + k;
+                    const int64_t at = node * K + k;
                     a.y[at] = store_as<TU>::from(cvt<A>(a.x[at]) - pick<K>(z, k));
                 }
             }
@@ -139,6 +143,7 @@ template <typename TW, typename OffT> struct PowerArgs {
     float* y;
     const float* scale;
     float* partials;  // [2][grid]
+    const int32_t* order;
     RowGeom g;
     int32_t mode;
 };
@@ -158,11 +163,12 @@ __global__ __launch_bounds__(kBlock) void power_kernel(PowerArgs<TW, OffT> a) {
         float z[1];
         row_gather<1>(a.rp, a.col, a.w, a.x, row, a.g.n, q, G, z);
         if (row < a.g.n && q == 0) {
-            const float xv = a.x[row];
+            const int64_t node = a.order ? (int64_t)a.order[row] : row;
+            const float xv = a.x[node];
             const float lx = xv - z[0];
             if (a.mode == 0) {
                 const float yv = s * lx;
-                a.y[row] = yv;
+                a.y[node] = yv;
                 p0 += yv * yv;
             } else {
                 p0 += xv * lx;

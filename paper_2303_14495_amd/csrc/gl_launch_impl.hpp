@@ -5,6 +5,7 @@
 
 #include "gl_internal.hpp"
 #include "gl_kernels.hpp"
+#include "gl_tile.hpp"
 
 namespace gl {
 
@@ -19,6 +20,7 @@ static SweepArgs<TW, TU, OffT> make_sweep_args(const SweepLaunch& L) {
     a.vin = static_cast<const TU*>(L.vin);
     a.vout = static_cast<TU*>(L.vout);
     a.labels = L.labels;
+    a.order = L.r.order;
     a.partials = static_cast<A*>(L.partials);
     a.g = RowGeom{L.r.n, L.r.rows_per_block, L.r.G, L.r.log2G, L.r.tiles, L.r.remap};
     a.energy = L.energy;
@@ -38,8 +40,71 @@ static SweepArgs<TW, TU, OffT> make_sweep_args(const SweepLaunch& L) {
 
 #define GL_K_CASES(X) X(1) X(2) X(3) X(4) X(5) X(6) X(7) X(8) X(9) X(10) X(11) X(12) X(13) X(14) X(15) X(16)
 
+static TileOp tile_op(const RowLaunch& r) {
+    TileOp op;
+    op.rp = r.trp;
+    op.lcol = r.lcol;
+    op.w = r.w;
+    op.halo = r.halo;
+    op.hp = r.hp;
+    op.order = r.order;
+    op.n = r.n;
+    return op;
+}
+
+template <typename TW, typename TU>
+static hipError_t tile_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
+    typedef typename acc_of<TU>::type A;
+    TileSweepArgs<TU, A> a;
+    a.op = tile_op(L.r);
+    a.ut = static_cast<const TU*>(L.ut);
+    a.vin = static_cast<const TU*>(L.vin);
+    a.vout = static_cast<TU*>(L.vout);
+    a.labels = L.labels;
+    a.partials = static_cast<A*>(L.partials);
+    a.energy = L.energy;
+    const SweepArgs<TW, TU, int32_t> d = make_sweep_args<TW, TU, int32_t>(L);
+    a.k = d.k;
+    const dim3 grid((unsigned)L.r.grid), block(kBlock);
+    const size_t lds = (size_t)L.r.hmax * K * sizeof(A);
+    switch (K) {
+#define GL_CASE(KK)                                                                       \
+    case KK:                                                                              \
+        hipLaunchKernelGGL((tile_sweep_kernel<KK, TW, TU>), grid, block, lds, s, a);     \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TW, typename TU>
+static hipError_t tile_laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
+    typedef typename acc_of<TU>::type A;
+    TileLapArgs<TU> a;
+    a.op = tile_op(r);
+    a.x = static_cast<const TU*>(x);
+    a.y = static_cast<TU*>(y);
+    const dim3 grid((unsigned)r.grid), block(kBlock);
+    const size_t lds = (size_t)r.hmax * K * sizeof(A);
+    switch (K) {
+#define GL_CASE(KK)                                                                        \
+    case KK:                                                                               \
+        hipLaunchKernelGGL((tile_laplacian_kernel<KK, TW, TU>), grid, block, lds, s, a);  \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename TW, typename TU, typename OffT>
 static hipError_t sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
+    if (L.r.layout == LAYOUT_TILE) return tile_sweep_k<TW, TU>(K, L, s);
     const SweepArgs<TW, TU, OffT> a = make_sweep_args<TW, TU, OffT>(L);
     const dim3 grid((unsigned)L.r.grid), block(kBlock);
     switch (K) {
@@ -57,12 +122,14 @@ static hipError_t sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
 
 template <typename TW, typename TU, typename OffT>
 static hipError_t laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
+    if (r.layout == LAYOUT_TILE) return tile_laplacian_k<TW, TU>(K, r, x, y, s);
     LapArgs<TW, TU, OffT> a;
     a.rp = static_cast<const OffT*>(r.rp);
     a.col = r.col;
     a.w = static_cast<const TW*>(r.w);
     a.x = static_cast<const TU*>(x);
     a.y = static_cast<TU*>(y);
+    a.order = r.order;
     a.g = RowGeom{r.n, r.rows_per_block, r.G, r.log2G, r.tiles, r.remap};
     const dim3 grid((unsigned)r.grid), block(kBlock);
     switch (K) {

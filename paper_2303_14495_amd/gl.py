@@ -37,7 +37,11 @@ class GLError(RuntimeError):
 class _Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p),
-                ("weight_dtype", ctypes.c_int32)]
+                ("weight_dtype", ctypes.c_int32), ("order", ctypes.c_void_p),
+                ("layout", ctypes.c_int32)]
+
+
+LAYOUTS = {"auto": 0, "direct": 1, "tile": 2}
 
 
 class _Params(ctypes.Structure):
@@ -57,6 +61,7 @@ SIGNATURES = {
     "gl_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "gl_operator_destroy": (ctypes.c_int, [_P]),
     "gl_operator_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "gl_operator_layout": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gl_laplacian_apply": (ctypes.c_int, [_P, _I32, _I32, _P, _P, _P]),
     "gl_power_workspace_size": (ctypes.c_int, [_P, _P]),
     "gl_power_max_eig": (ctypes.c_int, [_P, _I32, _P, _P, _SZ, _P, _P, _P]),
@@ -121,7 +126,8 @@ class Operator:
     [nnz]) are CUDA tensors of a symmetric graph without self-loops.
     """
 
-    def __init__(self, row_ptr, col, weight, store_w: str = "f32", stream=None):
+    def __init__(self, row_ptr, col, weight, store_w: str = "f32", stream=None, order=None,
+                 layout: str = "auto"):
         lib = load_library()
         if not (row_ptr.is_cuda and col.is_cuda and weight.is_cuda):
             raise ValueError("graph tensors must live on the GPU")
@@ -135,8 +141,12 @@ class Operator:
         self.nnz = int(col.numel())
         self.store_w = store_w
         self.device = row_ptr.device
+        order_t = None
+        if order is not None:
+            order_t = order.to(device=row_ptr.device, dtype=torch.int32).contiguous()
         g = _Graph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
-                   self.weight.data_ptr(), DTYPES[DTYPE_OF_TORCH[weight.dtype]])
+                   self.weight.data_ptr(), DTYPES[DTYPE_OF_TORCH[weight.dtype]],
+                   order_t.data_ptr() if order_t is not None else None, LAYOUTS[layout])
         handle = ctypes.c_void_p()
         self._h = None
         _check(lib.gl_operator_create(ctypes.byref(g), DTYPES[store_w], _stream_handle(stream),
@@ -167,8 +177,15 @@ class Operator:
         _check(load_library().gl_operator_info(self._h, ctypes.byref(n), ctypes.byref(nnz),
                                                ctypes.byref(sw), ctypes.byref(lanes),
                                                ctypes.byref(by)))
+        lay, stored, hmax, htot, sb = (ctypes.c_int32(), ctypes.c_int64(), ctypes.c_int32(),
+                                       ctypes.c_int64(), ctypes.c_int64())
+        _check(load_library().gl_operator_layout(self._h, ctypes.byref(lay), ctypes.byref(stored),
+                                                 ctypes.byref(hmax), ctypes.byref(htot),
+                                                 ctypes.byref(sb)))
         return {"n": n.value, "nnz": nnz.value, "lanes_per_row": lanes.value,
-                "device_bytes": by.value}
+                "device_bytes": by.value,
+                "layout": {1: "direct", 2: "tile"}[lay.value], "stored_entries": stored.value,
+                "halo_max": hmax.value, "halo_total": htot.value, "stream_bytes": sb.value}
 
     def _workspace(self, key, nbytes):
         ws = self._ws.get(key)

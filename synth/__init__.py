@@ -20,5 +20,6 @@ from .graphs import (  # noqa: F401
     random_labels,
     initial_u,
     tiny_graph,
+    zorder,
 )
 from .configs import Problem, make_problem, CONFIG_NAMES  # noqa: F401

@@ -122,6 +122,20 @@ def textured_regions_image(h: int, w: int, nregions: int,
     return img, truth
 
 
+def zorder(h: int, w: int) -> np.ndarray:
+    """Z-order (Morton) visit order of an h x w pixel grid, as row-major pixel
+    ids: position p of the returned int32 array holds the pixel visited p-th.
+    Any aligned 4^j-long run of positions covers a 2^j x 2^j square when h and
+    w are powers of two."""
+    yy, xx = np.meshgrid(np.arange(h, dtype=np.int64), np.arange(w, dtype=np.int64),
+                         indexing="ij")
+    code = np.zeros((h, w), dtype=np.int64)
+    for bit in range(32):
+        code |= ((xx >> bit) & 1) << (2 * bit)
+        code |= ((yy >> bit) & 1) << (2 * bit + 1)
+    return np.argsort(code.reshape(-1), kind="stable").astype(np.int32)
+
+
 def patch_features(img: np.ndarray, size: int = 3) -> np.ndarray:
     """Stack the size x size RGB patch around each pixel (edge-replicate pad).
 

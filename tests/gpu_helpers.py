@@ -44,10 +44,12 @@ def oracle_lambda(p, iters=150):
     return rq, lam
 
 
-def make_operator(p, store_w):
+def make_operator(p, store_w, layout="auto", use_order=True):
     g = p.graph
+    order = getattr(p, "order", None) if use_order else None
     return gl.Operator(g.row_ptr.to(DEV), g.col.to(DEV), g.weight.to(DEV).to(torch.float64),
-                       store_w=store_w)
+                       store_w=store_w, layout=layout,
+                       order=torch.from_numpy(order).to(DEV) if order is not None else None)
 
 
 def gpu_solve(p, store_w, store_u, lambda_max=2.0, outer=None, sweeps=None, u0=None,
