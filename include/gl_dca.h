@@ -1,7 +1,11 @@
 /*
  * gl_dca.h -- C ABI of the MI355X (gfx950) preconditioned-DCA library for the
- * graph Ginzburg-Landau model of Shen, Sun and Tai, "Preconditioned DCA for
- * the graph Ginzburg-Landau model" (arXiv 2303.14495).
+ * graph Ginzburg-Landau model of Shen, Sun and Tai, "Preconditioned Algorithm
+ * for Difference of Convex Functions with applications to Graph
+ * Ginzburg-Landau Model" (arXiv 2303.14495).  Citations name the paper's
+ * sections, propositions (Prop. 1: the preconditioned iteration of the
+ * proximal DCA; Prop. 3: 2I >= L_s), Lemma 1 (step size k) and Theorem 1
+ * (energy decay).
  *
  * The library computes the inner linear solve of every DCA step,
  *     (eps L_s + eta Lambda + c I) u^{t+1} = c u^t - (u^t^3 - u^t)/eps + eta Lambda y,
@@ -218,6 +222,91 @@ gl_status gl_time_sweeps(const gl_operator *op, const gl_params *params, int32_t
  * K >= 2 -> argmax_k u_ik, ties to the lowest k.  labels_out: device int32 [n]. */
 gl_status gl_assign_labels(int64_t n, int32_t K, gl_dtype dtype, const void *U,
                            int32_t *labels_out, void *stream);
+
+/* ------------------------------------------------------------------------
+ * Continuous-batching server.  Requests (host arrays) are queued by
+ * gl_server_submit; a loader thread admits them in arrival order while a
+ * solve slot is free and the request's device footprint fits in the server's
+ * HBM arena, copies them to the GPU and builds their operators (direct
+ * layout); a scheduler thread advances every admitted solve by one sweep per
+ * "tick" with ONE batched kernel launch over all of them (plus one batched
+ * statistics launch), so requests that arrive while others run join at the
+ * next tick; a finisher thread copies results back and frees the slot and
+ * memory.  Each solve computes exactly what gl_solve computes for it (same
+ * kernels, same per-row order): results are bitwise equal to a gl_solve of
+ * the same request, alone or in any mix.
+ * ------------------------------------------------------------------------ */
+typedef struct gl_server gl_server;
+
+typedef struct gl_server_config {
+    size_t hbm_budget_bytes;  /* device arena for admitted solves, allocated at creation */
+    int32_t max_slots;        /* solves on the GPU at once, 1..64 */
+    int32_t max_pending;      /* queued, not yet admitted requests (>= 1) */
+    int32_t store_w;          /* gl_dtype of the weights: GL_F32, GL_BF16 or GL_F16 */
+    int32_t store_u;          /* gl_dtype of the field: GL_F32, GL_BF16 or GL_F16 */
+    int32_t ticks_in_flight;  /* batched launches queued ahead of the GPU, 1..8 */
+    int32_t reserved;         /* must be 0 */
+} gl_server_config;
+
+typedef struct gl_request {   /* HOST arrays, copied by gl_server_submit */
+    int64_t n;
+    int64_t nnz;
+    const int64_t *row_ptr;   /* as in gl_graph */
+    const int32_t *col_idx;
+    const double *weight;
+    const int32_t *labels;    /* n, as in gl_solve */
+    const float *u0;          /* n x K */
+    int32_t K;                /* 1..10 */
+    int32_t reserved;         /* must be 0 */
+    gl_params params;
+} gl_request;
+
+typedef struct gl_result {    /* filled by gl_server_poll */
+    float *U;                 /* caller's host n x K buffer for u^T, or NULL */
+    int32_t *labels;          /* caller's host n buffer for the classes, or NULL */
+    double *stats;            /* caller's host gl_stats_length(K, T, m) buffer, or NULL */
+    double t_submit;          /* seconds since the server was created */
+    double t_admit;
+    double t_done;
+    int32_t status;           /* gl_status of this solve (GL_E_NONFINITE, GL_E_BAD_GRAPH, ...) */
+    int32_t reserved;
+} gl_result;
+
+/* Create a server on the current device.  Errors: GL_E_INVALID_ARG, GL_E_NOMEM. */
+gl_status gl_server_create(const gl_server_config *cfg, gl_server **out);
+
+/* Queue a request; *ticket identifies it.  GL_E_QUEUE_FULL when max_pending
+ * requests wait; GL_E_BUDGET when its footprint exceeds the whole arena;
+ * GL_E_INVALID_ARG for malformed sizes/params (graph content is checked on
+ * the GPU at admission and reported through the result status). */
+gl_status gl_server_submit(gl_server *srv, const gl_request *req, uint64_t *ticket);
+
+/* Result of a ticket.  wait = 0: GL_E_NOT_READY while it runs; wait != 0:
+ * block until done.  On GL_OK the ticket is consumed and out->status holds
+ * the solve's own status. */
+gl_status gl_server_poll(gl_server *srv, uint64_t ticket, int32_t wait, gl_result *out);
+
+/* Cancel a ticket: a queued request ends at once, an admitted one stops at
+ * the next tick; its result status becomes GL_E_CANCELLED.  A request that has
+ * already finished keeps its result.  The ticket must still be polled. */
+gl_status gl_server_cancel(gl_server *srv, uint64_t ticket);
+
+/* Arena bytes a request of these sizes takes in a server with this storage:
+ * `peak` while it is being admitted (graph copy included), `held` from then
+ * until it finishes (host out).  A request is refused with GL_E_BUDGET when
+ * `peak` exceeds hbm_budget_bytes.  Touches no GPU.  Errors: GL_E_INVALID_ARG,
+ * GL_E_DTYPE. */
+gl_status gl_server_request_bytes(int64_t n, int64_t nnz, int32_t K, int32_t outer_steps,
+                                  int32_t inner_sweeps, gl_dtype store_w, gl_dtype store_u,
+                                  size_t *peak, size_t *held);
+
+/* Host counters: queued, on the GPU, finished-unpolled, arena bytes in use,
+ * batched ticks launched.  Any pointer may be NULL. */
+gl_status gl_server_info(gl_server *srv, int64_t *pending, int64_t *active, int64_t *finished,
+                         size_t *arena_used, int64_t *ticks);
+
+/* Drain: queued requests are cancelled, admitted ones finish; then free all. */
+gl_status gl_server_destroy(gl_server *srv);
 
 /* Message of the last non-OK status returned to the calling thread. */
 const char *gl_last_error(void);

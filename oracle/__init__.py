@@ -1,6 +1,6 @@
 """CPU float64 oracle for the preconditioned DCA of the graph Ginzburg-Landau
-model (Shen, Sun, Tai: "Preconditioned DCA for the graph Ginzburg-Landau
-model", arXiv 2303.14495).
+model (Shen, Sun, Tai: "Preconditioned Algorithm for Difference of Convex
+Functions with applications to Graph Ginzburg-Landau Model", arXiv 2303.14495).
 
 TEST INFRASTRUCTURE ONLY.  Nothing in the product package may import, call,
 link or execute anything here; only the tests, the smoke check and the CPU

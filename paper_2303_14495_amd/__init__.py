@@ -7,6 +7,7 @@ this package holds its sources, its build script and a thin ctypes binding.
 from .gl import (  # noqa: F401
     GLError,
     Operator,
+    Server,
     assign_labels,
     load_library,
     split_stats,

@@ -43,6 +43,12 @@ gl_status fail(gl_status st, const std::string& msg) {
     return st;
 }
 
+}  // namespace
+
+void gl::set_last_error(const std::string& msg) { g_err = msg; }
+
+namespace {
+
 #define GL_HIP(expr, what)                                                                \
     do {                                                                                  \
         hipError_t e_ = (expr);                                                           \

@@ -4,6 +4,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <string>
+
 #include "../../include/gl_dca.h"
 
 namespace gl {
@@ -44,6 +46,9 @@ struct SweepLaunch {
     // eps, c, eta, 1/eps, eps/2, 1/(4 eps), eta/2, 1/g0, 1/g1, alpha, kappa
     double coef[11];
 };
+
+// Thread-local message returned by gl_last_error().
+void set_last_error(const std::string& msg);
 
 // Each returns hipSuccess or the launch error; hipErrorInvalidValue when the
 // (weight type, K) combination is not compiled for this field type.

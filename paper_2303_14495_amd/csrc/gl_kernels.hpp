@@ -43,16 +43,15 @@ template <typename TW, typename TU, typename OffT> struct SweepArgs {
     SweepCoef<A> k;
 };
 
-// One sweep (or the energy-only pass) for K columns.
+// One sweep (or the energy-only pass) over logical block b of nb blocks.
 template <int K, typename TW, typename TU, typename OffT>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a) {
+__device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, int64_t b, int64_t nb) {
     typedef typename acc_of<TU>::type A;
     constexpr int CPL = (K + 3) / 4;  // columns per lane (G >= 4)
     const int G = a.g.G;
     const int q = threadIdx.x & (G - 1);
     const int grp = threadIdx.x >> a.g.log2G;
     const int rows_per_tile = kBlock >> a.g.log2G;
-    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
     const int64_t row0 = b * a.g.rows_per_block;
     A e_acc[CPL], r_acc[CPL];
 #pragma unroll
@@ -91,7 +90,14 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a
             }
         }
     }
-    if (a.partials) block_stats<K, CPL>(e_acc, r_acc, G, a.partials, (int64_t)gridDim.x, b);
+    if (a.partials) block_stats<K, CPL>(e_acc, r_acc, G, a.partials, nb, b);
+}
+
+// One sweep (or the energy-only pass) for K columns.
+template <int K, typename TW, typename TU, typename OffT>
+__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a) {
+    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
+    sweep_block<K>(a, b, (int64_t)gridDim.x);
 }
 
 // Y = X - What X  (L_s X, Section 2.2)

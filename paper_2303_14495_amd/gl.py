@@ -52,6 +52,27 @@ class _Params(ctypes.Structure):
                 ("reserved", ctypes.c_int32)]
 
 
+class _ServerConfig(ctypes.Structure):
+    _fields_ = [("hbm_budget_bytes", ctypes.c_size_t), ("max_slots", ctypes.c_int32),
+                ("max_pending", ctypes.c_int32), ("store_w", ctypes.c_int32),
+                ("store_u", ctypes.c_int32), ("ticks_in_flight", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
+class _Request(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
+                ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p),
+                ("labels", ctypes.c_void_p), ("u0", ctypes.c_void_p), ("K", ctypes.c_int32),
+                ("reserved", ctypes.c_int32), ("params", _Params)]
+
+
+class _Result(ctypes.Structure):
+    _fields_ = [("U", ctypes.c_void_p), ("labels", ctypes.c_void_p), ("stats", ctypes.c_void_p),
+                ("t_submit", ctypes.c_double), ("t_admit", ctypes.c_double),
+                ("t_done", ctypes.c_double), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+
 _lib = None
 
 # symbol -> (restype, argtypes)
@@ -71,6 +92,15 @@ SIGNATURES = {
     "gl_assign_labels": (ctypes.c_int, [_I64, _I32, _I32, _P, _P, _P]),
     "gl_params_validate": (ctypes.c_int, [_P]),
     "gl_time_sweeps": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _P, _P, _SZ, _I32, _P, _P]),
+    "gl_server_create": (ctypes.c_int, [_P, _P]),
+    "gl_server_submit": (ctypes.c_int, [_P, _P, _P]),
+    "gl_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _I32, _P]),
+    "gl_server_cancel": (ctypes.c_int, [_P, ctypes.c_uint64]),
+    "gl_server_request_bytes": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int32,
+                                               ctypes.c_int32, ctypes.c_int32, ctypes.c_int,
+                                               ctypes.c_int, _P, _P]),
+    "gl_server_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
+    "gl_server_destroy": (ctypes.c_int, [_P]),
     "gl_last_error": (ctypes.c_char_p, []),
     "gl_version": (ctypes.c_char_p, []),
 }
@@ -270,6 +300,88 @@ def assign_labels(U: torch.Tensor, stream=None) -> torch.Tensor:
                                            DTYPES[DTYPE_OF_TORCH[U2.dtype]], _ptr(U2), _ptr(out),
                                            _stream_handle(stream)))
     return out
+
+
+class Server:
+    """Continuous-batching server (gl_server_*): host requests in, host results out."""
+
+    def __init__(self, hbm_budget_bytes: int, max_slots: int = 32, max_pending: int = 1024,
+                 store_w: str = "bf16", store_u: str = "bf16", ticks_in_flight: int = 2):
+        lib = load_library()
+        cfg = _ServerConfig(hbm_budget_bytes, max_slots, max_pending, DTYPES[store_w],
+                            DTYPES[store_u], ticks_in_flight, 0)
+        h = ctypes.c_void_p()
+        self._h = None
+        _check(lib.gl_server_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self._h = h
+        self._meta = {}
+
+    def submit(self, row_ptr, col, weight, labels, u0, *, eps, c, eta, precond, outer, sweeps,
+               delta0=1e-6, lambda_max=2.0, step_k=math.inf) -> int:
+        import numpy as np
+        rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
+        cl = np.ascontiguousarray(col, dtype=np.int32)
+        w = np.ascontiguousarray(weight, dtype=np.float64)
+        lab = np.ascontiguousarray(labels, dtype=np.int32)
+        U0 = np.ascontiguousarray(u0, dtype=np.float32)
+        if U0.ndim == 1:
+            U0 = U0[:, None].copy()
+        n, K = U0.shape
+        p = _Params(eps, c, eta, delta0, lambda_max, step_k, PRECONDS[precond], outer, sweeps, 0)
+        req = _Request(n, cl.size, rp.ctypes.data, cl.ctypes.data, w.ctypes.data, lab.ctypes.data,
+                       U0.ctypes.data, K, 0, p)
+        t = ctypes.c_uint64()
+        _check(load_library().gl_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
+        self._meta[t.value] = (n, K, outer, sweeps)
+        return t.value
+
+    def poll(self, ticket: int, wait: bool = True):
+        """Result dict, or None while not ready (wait=False)."""
+        import numpy as np
+        if ticket not in self._meta:
+            raise GLError(1, "unknown or consumed ticket")
+        n, K, T, m = self._meta[ticket]
+        U = np.empty((n, K), dtype=np.float32)
+        lab = np.empty(n, dtype=np.int32)
+        st = np.empty(stats_length(K, T, m), dtype=np.float64)
+        r = _Result(U.ctypes.data, lab.ctypes.data, st.ctypes.data, 0, 0, 0, 0, 0)
+        rc = load_library().gl_server_poll(self._h, ticket, 1 if wait else 0, ctypes.byref(r))
+        if rc == 9:  # GL_E_NOT_READY
+            return None
+        _check(rc)
+        del self._meta[ticket]
+        return {"status": STATUS.get(r.status, r.status), "U": U, "labels": lab, "stats": st,
+                "t_submit": r.t_submit, "t_admit": r.t_admit, "t_done": r.t_done}
+
+    @staticmethod
+    def request_bytes(n, nnz, K, outer, sweeps, store_w="bf16", store_u="bf16"):
+        """(peak, held) arena bytes of a request (gl_server_request_bytes)."""
+        peak, held = ctypes.c_size_t(), ctypes.c_size_t()
+        _check(load_library().gl_server_request_bytes(n, nnz, K, outer, sweeps, DTYPES[store_w],
+                                                      DTYPES[store_u], ctypes.byref(peak),
+                                                      ctypes.byref(held)))
+        return peak.value, held.value
+
+    def cancel(self, ticket: int):
+        _check(load_library().gl_server_cancel(self._h, ticket))
+
+    def info(self) -> dict:
+        v = [ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t(),
+             ctypes.c_int64()]
+        _check(load_library().gl_server_info(self._h, *[ctypes.byref(x) for x in v]))
+        return dict(zip(("pending", "active", "finished", "arena_used", "ticks"),
+                        [x.value for x in v]))
+
+    def close(self):
+        if getattr(self, "_h", None) is not None:
+            load_library().gl_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def version() -> str:

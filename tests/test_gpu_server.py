@@ -1,0 +1,263 @@
+"""GPU tests of the continuous-batching server (gl_server_*).
+
+A served solve runs the same direct-layout sweep as gl_solve, batched with the
+other admitted solves into one launch per tick, so every served result must be
+bitwise equal to gl_solve on the same request alone (direct layout, natural
+order, same storage) -- whatever else shares its ticks -- and within the
+low-precision tolerance of the float64 oracle.  Failure cases (bad graph,
+non-finite input, cancellation, budget, queue limit) must stay with the request
+that caused them.
+"""
+
+from __future__ import annotations
+
+import time
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2303_14495_amd as gl
+from synth.configs import StreamItem, served_problem
+from tests.gpu_helpers import DEV, label_agreement, say
+from oracle import c_oracle
+
+pytestmark = pytest.mark.gpu
+
+_SERVED = {}
+
+
+def served(index, n, K, knn_k=12):
+    key = (index, n, K, knn_k)
+    if key not in _SERVED:
+        say(f"building served request {key}")
+        _SERVED[key] = served_problem(StreamItem(index, n, K, knn_k, 0.0), device=DEV)
+    return _SERVED[key]
+
+
+def params(p, **over):
+    kw = dict(eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=p.outer, sweeps=p.sweeps,
+              delta0=p.delta0, lambda_max=2.0)
+    kw.update(over)
+    return kw
+
+
+def submit(srv, p, u0=None, graph=None, **over):
+    rp, col, w = graph if graph is not None else p.graph.numpy()
+    return srv.submit(rp, col, w, p.labels, p.u0 if u0 is None else u0, **params(p, **over))
+
+
+def alone(p, store_w, store_u, **over):
+    """gl_solve on the same request: direct layout, natural order."""
+    g = p.graph
+    op = gl.Operator(g.row_ptr.to(DEV), g.col.to(DEV), g.weight.to(DEV).to(torch.float64),
+                     store_w=store_w, layout="direct")
+    kw = params(p, **over)
+    U = torch.from_numpy(np.ascontiguousarray(p.u0, dtype=np.float32)).to(DEV).to(
+        gl.TORCH_DTYPES[store_u]).contiguous()
+    lab = torch.from_numpy(np.ascontiguousarray(p.labels, dtype=np.int32)).to(DEV)
+    st = op.solve(lab, U, stats=True, **kw)
+    classes = gl.assign_labels(U)
+    torch.cuda.synchronize()
+    out = (U.float().cpu().numpy(), st.cpu().numpy(), classes.cpu().numpy())
+    op.close()
+    return out
+
+
+def assert_same_as_alone(res, ref, tag):
+    U, st, cl = ref
+    assert res["status"] == "GL_OK", (tag, res["status"])
+    assert np.array_equal(res["U"].view(np.uint32), U.view(np.uint32)), f"{tag}: U differs"
+    assert np.array_equal(res["stats"].view(np.uint64), st.view(np.uint64)), f"{tag}: stats differ"
+    assert np.array_equal(res["labels"], cl), f"{tag}: classes differ"
+
+
+def oracle(p, **over):
+    rp, col, w = p.graph.numpy()
+    kw = params(p, **over)
+    return c_oracle.dca_solve(p.n, rp, col, w, p.labels, p.u0, eps=kw["eps"], c=kw["c"],
+                              eta=kw["eta"], precond=kw["precond"], outer=kw["outer"],
+                              sweeps=kw["sweeps"], delta0=kw["delta0"],
+                              lambda_max=kw["lambda_max"])
+
+
+@pytest.mark.parametrize("store_w,store_u", [("bf16", "bf16"), ("f32", "f32"), ("bf16", "f16")])
+def test_single_request_equals_solve(store_w, store_u):
+    p = served(0, 2500, 4)
+    say(f"single request {store_w}/{store_u} n={p.n} nnz={p.graph.nnz}")
+    srv = gl.Server(256 << 20, max_slots=4, store_w=store_w, store_u=store_u)
+    try:
+        t = submit(srv, p)
+        res = srv.poll(t)
+        assert_same_as_alone(res, alone(p, store_w, store_u), "single")
+        assert res["t_submit"] <= res["t_admit"] <= res["t_done"]
+        info = srv.info()
+        assert info["active"] == 0 and info["arena_used"] == 0 and info["ticks"] == 20 * 4 + 1
+    finally:
+        srv.close()
+    Uo, eo, _ = oracle(p)
+    tol = 1e-5 if store_u == "f32" else 2e-2
+    err = float(np.abs(res["U"] - Uo).max())
+    say(f"  max|U - oracle| = {err:.3e}")
+    assert err <= tol
+    assert label_agreement(res["U"], Uo) >= 0.999
+    e = res["stats"][: (p.outer + 1) * p.K].reshape(p.outer + 1, p.K)
+    assert np.abs(e - eo).max() <= (1e-4 if store_u == "f32" else 2e-2) * np.abs(eo).max()
+
+
+MIX = [(1, 1200, 2, 10), (2, 4000, 10, 20), (3, 2500, 5, 14), (4, 800, 3, 11),
+       (5, 6000, 7, 16), (6, 3000, 9, 18), (7, 1500, 6, 12), (8, 5000, 8, 15)]
+
+
+def test_mix_each_equals_alone():
+    """Eight requests of different N, K and k through four slots: every one
+    matches its own solve alone bitwise, and the oracle within tolerance."""
+    probs = [served(i, n, K, k) for (i, n, K, k) in MIX]
+    srv = gl.Server(512 << 20, max_slots=4, store_w="bf16", store_u="bf16")
+    try:
+        tickets = [submit(srv, p) for p in probs]
+        results = [srv.poll(t) for t in tickets]
+        info = srv.info()
+        assert info["arena_used"] == 0 and info["active"] == 0
+        # the ticks were shared: fewer ticks than the solves need one after another
+        assert info["ticks"] < len(probs) * (20 * 4 + 1)
+    finally:
+        srv.close()
+    for (i, n, K, k), p, res in zip(MIX, probs, results):
+        say(f"  request {i}: n={n} K={K} k={k}")
+        assert_same_as_alone(res, alone(p, "bf16", "bf16"), f"request {i}")
+        Uo = oracle(p)[0]
+        assert float(np.abs(res["U"] - Uo).max()) <= 2e-2
+        assert label_agreement(res["U"], Uo) >= 0.999
+
+
+def test_budget_serialises_admission():
+    """An arena that holds one request at a time still serves all of them, in
+    order, with the same results; a request above the budget is refused."""
+    p = served(2, 4000, 10, 20)
+    peak, held = gl.Server.request_bytes(p.n, p.graph.nnz, p.K, p.outer, p.sweeps)
+    assert held < peak
+    srv = gl.Server(peak + 256, max_slots=8, store_w="bf16", store_u="bf16")
+    try:
+        big = served(9, 20000, 10, 20)
+        with pytest.raises(gl.GLError) as ei:
+            submit(srv, big)
+        assert ei.value.status == 5  # GL_E_BUDGET
+        tickets = [submit(srv, p) for _ in range(3)]
+        results = [srv.poll(t) for t in tickets]
+    finally:
+        srv.close()
+    ref = alone(p, "bf16", "bf16")
+    for res in results:
+        assert_same_as_alone(res, ref, p.name)
+    # one at a time, in arrival order: each admitted only after the previous finished
+    for a, b in zip(results, results[1:]):
+        assert b["t_admit"] >= a["t_done"]
+
+
+def test_bad_graph_and_nonfinite_are_isolated():
+    good = [served(i, n, K, k) for (i, n, K, k) in MIX[:2]]
+    bad = served(10, 1000, 3, 10)
+    rp, col, w = bad.graph.numpy()
+    w_asym = w.copy()
+    w_asym[5] *= 1.5  # breaks symmetry of one weight
+    col_oob = col.copy()
+    col_oob[7] = bad.n + 3  # column out of range
+    u_nan = bad.u0.copy()
+    u_nan[0, 0] = np.nan
+    srv = gl.Server(256 << 20, max_slots=4, store_w="bf16", store_u="bf16")
+    try:
+        t0 = submit(srv, good[0])
+        t_asym = submit(srv, bad, graph=(rp, col, w_asym))
+        t_oob = submit(srv, bad, graph=(rp, col_oob, w))
+        t_nan = submit(srv, bad, u0=u_nan)
+        t1 = submit(srv, good[1])
+        r0, ra, ro, rn, r1 = (srv.poll(t) for t in (t0, t_asym, t_oob, t_nan, t1))
+        assert srv.info()["arena_used"] == 0
+    finally:
+        srv.close()
+    assert ra["status"] == "GL_E_BAD_GRAPH"
+    assert ro["status"] == "GL_E_BAD_GRAPH"
+    assert rn["status"] == "GL_E_NONFINITE"
+    assert_same_as_alone(r0, alone(good[0], "bf16", "bf16"), "good 0")
+    assert_same_as_alone(r1, alone(good[1], "bf16", "bf16"), "good 1")
+
+
+def test_submit_rejects_malformed_requests():
+    p = served(0, 2500, 4)
+    rp, col, w = p.graph.numpy()
+    srv = gl.Server(64 << 20, max_slots=2)
+    try:
+        rp_bad = rp.copy()
+        rp_bad[-1] += 1
+        with pytest.raises(gl.GLError):
+            submit(srv, p, graph=(rp_bad, col, w))
+        with pytest.raises(gl.GLError):
+            submit(srv, p, eps=-1.0)
+        with pytest.raises(gl.GLError):
+            srv.submit(rp, col, w, p.labels, np.zeros((p.n, 11), np.float32), **params(p))
+        with pytest.raises(gl.GLError):
+            srv.poll(12345)
+    finally:
+        srv.close()
+
+
+def _wait_for(cond, timeout=30.0):
+    t_end = time.time() + timeout
+    while time.time() < t_end:
+        if cond():
+            return True
+        time.sleep(0.002)
+    return False
+
+
+def test_queue_full_and_cancel():
+    """One slot held by a long solve: the queue takes one more request and
+    refuses the next; cancelling the queued and the running request ends both
+    with GL_E_CANCELLED and frees the arena."""
+    p = served(0, 2500, 4)
+    srv = gl.Server(128 << 20, max_slots=1, max_pending=1)
+    try:
+        t_long = submit(srv, p, outer=2000, sweeps=8)
+        assert _wait_for(lambda: srv.info()["active"] == 1)
+        t_q = submit(srv, p)
+        assert srv.poll(t_long, wait=False) is None
+        with pytest.raises(gl.GLError) as ei:
+            submit(srv, p)
+        assert ei.value.status == 8  # GL_E_QUEUE_FULL
+        srv.cancel(t_q)
+        srv.cancel(t_long)
+        r_long, r_q = srv.poll(t_long), srv.poll(t_q)
+        assert r_long["status"] == "GL_E_CANCELLED"
+        assert r_q["status"] == "GL_E_CANCELLED"
+        assert _wait_for(lambda: srv.info()["arena_used"] == 0)
+        # the server keeps serving after cancellations
+        res = srv.poll(submit(srv, p))
+    finally:
+        srv.close()
+    assert_same_as_alone(res, alone(p, "bf16", "bf16"), "after cancel")
+
+
+def test_zero_steps_and_poll_without_wait():
+    p = served(0, 2500, 4)
+    srv = gl.Server(64 << 20, max_slots=2)
+    try:
+        t = submit(srv, p, outer=0)
+        res = None
+        assert _wait_for(lambda: srv.info()["finished"] == 1)
+        res = srv.poll(t, wait=False)
+    finally:
+        srv.close()
+    assert res is not None
+    assert_same_as_alone(res, alone(p, "bf16", "bf16", outer=0), "T = 0")
+
+
+def test_close_with_work_in_flight():
+    """Destroying the server with solves queued and running returns promptly."""
+    probs = [served(i, n, K, k) for (i, n, K, k) in MIX[:4]]
+    srv = gl.Server(256 << 20, max_slots=2)
+    for p in probs:
+        submit(srv, p)
+    t0 = time.time()
+    srv.close()
+    assert time.time() - t0 < 30.0
