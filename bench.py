@@ -49,6 +49,13 @@ def parse():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-fp32", action="store_true")
     ap.add_argument("--sweep-reps", type=int, default=40)
+    ap.add_argument("--no-served", action="store_true", help="skip the served stream")
+    ap.add_argument("--served-only", action="store_true")
+    ap.add_argument("--served-count", type=int, default=256)
+    ap.add_argument("--served-rate", type=float, default=0.8,
+                    help="arrival rate as a fraction of one-at-a-time f32 capacity")
+    ap.add_argument("--served-budget-gib", type=float, default=32.0)
+    ap.add_argument("--served-slots", type=int, default=32)
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -83,6 +90,183 @@ def timed_solves(op, labels, U, p, lam, steps, warmup):
     return wall, ev_ms, stats
 
 
+SERVED_PARAMS = dict(eps=100.0, c=11.0, eta=100.0, precond="damped_jacobi", outer=20, sweeps=4)
+
+
+class PinnedPool:
+    """Page-locked host staging for the request arrays: 1 GiB pinned buffers
+    carved into 256-byte aligned pieces (the way a server front end would
+    receive requests into DMA-able memory)."""
+
+    def __init__(self, chunk=1 << 30):
+        self.chunk, self.bufs, self.off = chunk, [], 0
+
+    def put(self, arr):
+        import numpy as np
+        import torch
+        arr = np.ascontiguousarray(arr)
+        nb = max(arr.nbytes, 1)
+        need = (nb + 255) // 256 * 256
+        if need > self.chunk:
+            buf, off = torch.empty(need, dtype=torch.uint8, pin_memory=True), 0
+            self.bufs.append(buf)
+        else:
+            if not self.bufs or self.off + need > self.chunk:
+                self.bufs.append(torch.empty(self.chunk, dtype=torch.uint8, pin_memory=True))
+                self.off = 0
+            buf, off = self.bufs[-1], self.off
+            self.off += need
+        t = buf[off:off + arr.nbytes].view(torch.from_numpy(arr[:0].copy()).dtype).view(arr.shape)
+        t.numpy()[...] = arr
+        return t
+
+
+def served_requests(dev, count, seed, pool):
+    """The served stream's requests in pinned host memory; graphs built on
+    the GPU with the library's exact kNN, then union-symmetrised with
+    self-tuning weights."""
+    import numpy as np
+    import torch
+    import paper_2303_14495_amd as gl
+    from synth.configs import served_problem, served_stream
+
+    def knn(x, k):
+        return gl.knn(x.to(torch.float32), k, with_distances=False)[0].to(torch.int64)
+
+    reqs = []
+    for item in served_stream(count, seed=seed):
+        p = served_problem(item, device=dev, knn=knn)
+        rp, col, w = p.graph.numpy()
+        r = {"n": p.n, "nnz": int(col.size), "K": p.K, "t": item.arrival, "truth": p.truth,
+             "rp": pool.put(rp), "col": pool.put(col), "w": pool.put(w),
+             "labels": pool.put(np.asarray(p.labels, dtype=np.int32)),
+             "u0": pool.put(np.asarray(p.u0, dtype=np.float32))}
+        reqs.append(r)
+        del p, rp, col, w
+    torch.cuda.synchronize()
+    return reqs
+
+
+def fp32_one(dev, r):
+    """One request alone, plain f32: upload, operator, solve, labels, download."""
+    import torch
+    import paper_2303_14495_amd as gl
+    op = gl.Operator(r["rp"].to(dev, non_blocking=True), r["col"].to(dev, non_blocking=True),
+                     r["w"].to(dev, non_blocking=True), store_w="f32")
+    U = r["u0"].to(dev, non_blocking=True)
+    lab = r["labels"].to(dev, non_blocking=True)
+    op.solve(lab, U, stats=True, **SERVED_PARAMS)
+    cls = gl.assign_labels(U).cpu().numpy()
+    U = U.cpu().numpy()
+    op.close()
+    return U, cls
+
+
+def run_fp32_stream(dev, reqs, arrivals):
+    """Requests one after another in arrival order (None: all at time 0);
+    returns (latencies s, makespan s, classes)."""
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lat, out = [], []
+    for i, r in enumerate(reqs):
+        a = 0.0 if arrivals is None else arrivals[i]
+        while time.perf_counter() - t0 < a:
+            time.sleep(min(1e-3, max(0.0, a - (time.perf_counter() - t0))))
+        _, cls = fp32_one(dev, r)
+        lat.append(time.perf_counter() - t0 - a)
+        out.append(cls)
+    return lat, time.perf_counter() - t0, out
+
+
+def run_served_stream(reqs, arrivals, budget, slots):
+    """Submit at the arrival times from one thread, collect from another;
+    returns (latencies s, makespan s, classes, server counters)."""
+    import threading
+    import paper_2303_14495_amd as gl
+    srv = gl.Server(budget, max_slots=slots, max_pending=len(reqs) + 1, store_w="bf16",
+                    store_u="bf16")
+    t_srv = time.perf_counter()  # the server's own clock starts at creation
+    tickets = [None] * len(reqs)
+    ready = threading.Semaphore(0)
+    res = [None] * len(reqs)
+
+    def collect():
+        for i in range(len(reqs)):
+            ready.acquire()
+            res[i] = srv.poll(tickets[i])
+
+    th = threading.Thread(target=collect)
+    th.start()
+    t0 = time.perf_counter()
+    for i, r in enumerate(reqs):
+        a = 0.0 if arrivals is None else arrivals[i]
+        while time.perf_counter() - t0 < a:
+            time.sleep(min(1e-3, max(0.0, a - (time.perf_counter() - t0))))
+        tickets[i] = srv.submit(r["rp"].numpy(), r["col"].numpy(), r["w"].numpy(),
+                                r["labels"].numpy(), r["u0"].numpy(), borrow=True,
+                                **SERVED_PARAMS)
+        ready.release()
+    th.join()
+    info = srv.info()
+    srv.close()
+    off = t0 - t_srv
+    lat = [(x["t_done"] - off) - (0.0 if arrivals is None else arrivals[i])
+           for i, x in enumerate(res)]
+    makespan = max(x["t_done"] for x in res) - off
+    bad = [x["status"] for x in res if x["status"] != "GL_OK"]
+    if bad:
+        raise RuntimeError(f"served requests failed: {bad[:5]}")
+    return lat, makespan, [x["labels"] for x in res], info
+
+
+def served_bench(dev, count, rate_factor, budget_gib, slots):
+    import numpy as np
+    log(f"served stream: generating {count} requests")
+    t = time.perf_counter()
+    pool = PinnedPool()
+    reqs = served_requests(dev, count, seed=4, pool=pool)
+    ns = [r["n"] for r in reqs]
+    log(f"  generated in {time.perf_counter() - t:.1f} s; N {min(ns)}..{max(ns)}, "
+        f"sum nnz {sum(r['nnz'] for r in reqs)}")
+    budget = int(budget_gib * (1 << 30))
+    # warm both paths on the first requests, then measure capacity (all at t = 0)
+    run_fp32_stream(dev, reqs[:4], None)
+    run_served_stream(reqs[:4], None, budget, slots)
+    lat32_cap, span32_cap, cls32 = run_fp32_stream(dev, reqs, None)
+    cap32 = count / span32_cap
+    lat_s_cap, span_s_cap, cls_s, info_cap = run_served_stream(reqs, None, budget, slots)
+    log(f"  capacity: fp32 one-at-a-time {cap32:.1f} solves/s, served bf16 "
+        f"{count / span_s_cap:.1f} solves/s ({info_cap['ticks']} ticks)")
+    # Poisson arrivals (unit-rate gaps of the stream scaled to the target rate)
+    rate = rate_factor * cap32
+    arrivals = [r["t"] / rate for r in reqs]
+    lat32, span32, _ = run_fp32_stream(dev, reqs, arrivals)
+    lat_s, span_s, _, info = run_served_stream(reqs, arrivals, budget, slots)
+    agree = float(np.mean([np.mean(a == b) for a, b in zip(cls_s, cls32)]))
+    acc_s = float(np.mean([np.mean(c == r["truth"]) for c, r in zip(cls_s, reqs)]))
+
+    def pct(v, q):
+        return float(np.percentile(np.asarray(v) * 1e3, q))
+
+    out = {
+        "requests": count, "rate_factor": rate_factor, "arrival_rate_per_s": rate,
+        "hbm_budget_gib": budget_gib, "max_slots": slots,
+        "served_bf16": {"solves_per_s": count / span_s, "p50_ms": pct(lat_s, 50),
+                        "p99_ms": pct(lat_s, 99), "capacity_solves_per_s": count / span_s_cap,
+                        "ticks": info["ticks"]},
+        "fp32_one_at_a_time": {"solves_per_s": count / span32, "p50_ms": pct(lat32, 50),
+                               "p99_ms": pct(lat32, 99), "capacity_solves_per_s": cap32},
+        "label_agreement_served_vs_fp32": agree,
+        "served_accuracy_vs_truth": acc_s,
+    }
+    log(f"  at {rate:.1f} req/s: served p50 {out['served_bf16']['p50_ms']:.1f} ms p99 "
+        f"{out['served_bf16']['p99_ms']:.1f} ms; fp32 p50 "
+        f"{out['fp32_one_at_a_time']['p50_ms']:.1f} ms p99 "
+        f"{out['fp32_one_at_a_time']['p99_ms']:.1f} ms; agreement {agree:.5f}")
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -97,6 +281,10 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.served_only:
+        print(json.dumps(served_bench(dev, args.served_count, args.served_rate,
+                                      args.served_budget_gib, args.served_slots)), flush=True)
+        return
     log(f"generating workload {args.workload}")
     t = time.perf_counter()
     p = make_problem(args.workload, device=dev)
@@ -182,6 +370,11 @@ def main():
                           f"float64, C+OpenMP) on the full graph, {t_step:.2f} s, "
                           f"scaled x{p.outer}")}
 
+    served = None
+    if not args.no_served:
+        served = served_bench(dev, args.served_count, args.served_rate, args.served_budget_gib,
+                              args.served_slots)
+
     B = main_res["sweep_bytes"]
     achieved = main_res["sweep_gbps"]
     out = {
@@ -213,13 +406,18 @@ def main():
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS, "traffic": None,
                      "kernel": "sweep_kernel", "bytes_per_launch": B},
         "cpu_baseline": cpu,
+        "served": served,
     }
     print(json.dumps(out), flush=True)
     if args.calib_copy:
-        src = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
+        # counter calibration: an elementwise kernel that reads 1 GiB and
+        # writes 1 GiB, far beyond the L2 and the Infinity Cache
+        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
-        dst.copy_(src)
         torch.cuda.synchronize()
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        log(f"calibration: mul over {src.numel() * 4} bytes in, {dst.numel() * 4} out")
 
 
 if __name__ == "__main__":

@@ -248,7 +248,10 @@ typedef struct gl_server_config {
     int32_t reserved;         /* must be 0 */
 } gl_server_config;
 
-typedef struct gl_request {   /* HOST arrays, copied by gl_server_submit */
+/* gl_request.flags */
+#define GL_REQ_BORROW 1 /* read the host arrays in place instead of copying them */
+
+typedef struct gl_request {   /* HOST arrays */
     int64_t n;
     int64_t nnz;
     const int64_t *row_ptr;   /* as in gl_graph */
@@ -257,7 +260,11 @@ typedef struct gl_request {   /* HOST arrays, copied by gl_server_submit */
     const int32_t *labels;    /* n, as in gl_solve */
     const float *u0;          /* n x K */
     int32_t K;                /* 1..10 */
-    int32_t reserved;         /* must be 0 */
+    int32_t flags;            /* 0: gl_server_submit copies the arrays and the caller may
+                                 reuse them at once.  GL_REQ_BORROW: the server reads them
+                                 in place; they must stay alive and unchanged until
+                                 gl_server_poll has returned this ticket's result.  Page-
+                                 locked memory (hipHostMalloc) then moves at DMA speed. */
     gl_params params;
 } gl_request;
 
@@ -307,6 +314,22 @@ gl_status gl_server_info(gl_server *srv, int64_t *pending, int64_t *active, int6
 
 /* Drain: queued requests are cancelled, admitted ones finish; then free all. */
 gl_status gl_server_destroy(gl_server *srv);
+
+/* ------------------------------------------------------------------------
+ * Graph construction: exact k nearest neighbours (Section 2.2 builds the
+ * clustering graphs from the k nearest neighbours in Euclidean distance;
+ * Section 6 names a parallel kNN as the missing piece for clustering).
+ *   x        device f32 [n x d], row-major feature vectors (caller-owned)
+ *   idx_out  device int32 [n x k]: for each point its k nearest other points
+ *            by ascending squared distance, ties to the lower index
+ *   d2_out   device f32 [n x k] or NULL: those squared distances, computed
+ *            as sum_c (x_ic - x_jc)^2 in f32 in coordinate order
+ * 1 <= d <= 64, 1 <= k <= 32, k < n < 2^31.  A point with a non-finite
+ * coordinate is never chosen as a neighbour; a list that cannot be filled
+ * ends with index -1 and distance +inf.  Asynchronous on `stream`.
+ * Errors: GL_E_INVALID_ARG, GL_E_HIP. */
+gl_status gl_knn(const float *x, int64_t n, int32_t d, int32_t k, int32_t *idx_out,
+                 float *d2_out, void *stream);
 
 /* Message of the last non-OK status returned to the calling thread. */
 const char *gl_last_error(void);

@@ -9,6 +9,7 @@ from .gl import (  # noqa: F401
     Operator,
     Server,
     assign_labels,
+    knn,
     load_library,
     split_stats,
     stats_length,

@@ -179,11 +179,16 @@ struct Solve {
     int64_t n = 0, nnz = 0;
     int32_t K = 1;
     gl_params p{};
-    std::vector<int64_t> rp;
+    std::vector<int64_t> rp;  // host copies (empty when the request is borrowed)
     std::vector<int32_t> col;
     std::vector<double> w;
     std::vector<int32_t> labels;
     std::vector<float> u0;
+    const int64_t* h_rp = nullptr;  // what the loader reads: the copies or the caller's arrays
+    const int32_t* h_col = nullptr;
+    const double* h_w = nullptr;
+    const int32_t* h_labels = nullptr;
+    const float* h_u0 = nullptr;
     gl::Footprint fp{};
     size_t off_raw = Arena::kNone, off_held = Arena::kNone;
     // device pointers inside the arena
@@ -370,11 +375,11 @@ struct gl_server {
             int32_t flags, pad;
             unsigned long long first;
         } fl = {0, 0, ~0ull};
-        hipError_t e = hipMemcpyAsync(s.d_rp64, s.rp.data(), (s.n + 1) * 8, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.d_colin, s.col.data(), s.nnz * 4, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.d_win, s.w.data(), s.nnz * 8, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.d_labels, s.labels.data(), s.n * 4, hipMemcpyHostToDevice, st);
-        if (e == hipSuccess) e = hipMemcpyAsync(s.d_u0, s.u0.data(), s.n * s.K * 4, hipMemcpyHostToDevice, st);
+        hipError_t e = hipMemcpyAsync(s.d_rp64, s.h_rp, (s.n + 1) * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.d_colin, s.h_col, s.nnz * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.d_win, s.h_w, s.nnz * 8, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.d_labels, s.h_labels, s.n * 4, hipMemcpyHostToDevice, st);
+        if (e == hipSuccess) e = hipMemcpyAsync(s.d_u0, s.h_u0, s.n * s.K * 4, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(s.d_flags, &fl, sizeof(fl), hipMemcpyHostToDevice, st);
         if (e != hipSuccess) {
             set_fatal(std::string("server copy: ") + hipGetErrorString(e));
@@ -392,6 +397,13 @@ struct gl_server {
             return e2;
         };
         auto drop_host_copies = [&]() {
+            s.h_rp = nullptr;
+            s.h_col = nullptr;
+            s.h_w = nullptr;
+            s.h_labels = nullptr;
+            s.h_u0 = nullptr;
+            s.labels.clear();
+            s.labels.shrink_to_fit();
             s.rp.clear();
             s.rp.shrink_to_fit();
             s.col.clear();
@@ -739,7 +751,7 @@ gl_status gl_server_submit(gl_server* srv, const gl_request* r, uint64_t* ticket
     if (r->n < 2 || r->n > INT32_MAX || r->nnz < 1 || r->nnz > INT32_MAX)
         return sfail(GL_E_INVALID_ARG, "served graphs need 2 <= n and 1 <= nnz < 2^31");
     if (r->K < 1 || r->K > gl::kServedKMax) return sfail(GL_E_INVALID_ARG, "served K must lie in [1, 10]");
-    if (r->reserved != 0) return sfail(GL_E_INVALID_ARG, "reserved must be 0");
+    if (r->flags & ~GL_REQ_BORROW) return sfail(GL_E_INVALID_ARG, "unknown request flags");
     if (gl_params_validate(&r->params) != GL_OK) return sfail(GL_E_INVALID_ARG, gl_last_error());
     if (r->row_ptr[0] != 0 || r->row_ptr[r->n] != r->nnz)
         return sfail(GL_E_INVALID_ARG, "row_ptr[0] must be 0 and row_ptr[n] must equal nnz");
@@ -759,11 +771,24 @@ gl_status gl_server_submit(gl_server* srv, const gl_request* r, uint64_t* ticket
         if ((int64_t)srv->pending.size() >= srv->cfg.max_pending) return sfail(GL_E_QUEUE_FULL, "pending queue is full");
         if (srv->stop) return sfail(GL_E_INVALID_ARG, "server is shutting down");
     }
-    s->rp.assign(r->row_ptr, r->row_ptr + r->n + 1);
-    s->col.assign(r->col_idx, r->col_idx + r->nnz);
-    s->w.assign(r->weight, r->weight + r->nnz);
-    s->labels.assign(r->labels, r->labels + r->n);
-    s->u0.assign(r->u0, r->u0 + r->n * r->K);
+    if (r->flags & GL_REQ_BORROW) {
+        s->h_rp = r->row_ptr;
+        s->h_col = r->col_idx;
+        s->h_w = r->weight;
+        s->h_labels = r->labels;
+        s->h_u0 = r->u0;
+    } else {
+        s->rp.assign(r->row_ptr, r->row_ptr + r->n + 1);
+        s->col.assign(r->col_idx, r->col_idx + r->nnz);
+        s->w.assign(r->weight, r->weight + r->nnz);
+        s->labels.assign(r->labels, r->labels + r->n);
+        s->u0.assign(r->u0, r->u0 + r->n * r->K);
+        s->h_rp = s->rp.data();
+        s->h_col = s->col.data();
+        s->h_w = s->w.data();
+        s->h_labels = s->labels.data();
+        s->h_u0 = s->u0.data();
+    }
     std::lock_guard<std::mutex> g(srv->mu);
     s->ticket = srv->next_ticket++;
     s->t_submit = now_since(srv->t0);

@@ -63,7 +63,7 @@ class _Request(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p),
                 ("labels", ctypes.c_void_p), ("u0", ctypes.c_void_p), ("K", ctypes.c_int32),
-                ("reserved", ctypes.c_int32), ("params", _Params)]
+                ("flags", ctypes.c_int32), ("params", _Params)]
 
 
 class _Result(ctypes.Structure):
@@ -101,6 +101,7 @@ SIGNATURES = {
                                                ctypes.c_int, _P, _P]),
     "gl_server_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gl_server_destroy": (ctypes.c_int, [_P]),
+    "gl_knn": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
     "gl_last_error": (ctypes.c_char_p, []),
     "gl_version": (ctypes.c_char_p, []),
 }
@@ -302,6 +303,20 @@ def assign_labels(U: torch.Tensor, stream=None) -> torch.Tensor:
     return out
 
 
+def knn(x: torch.Tensor, k: int, with_distances: bool = True, stream=None):
+    """Exact k nearest neighbours of every row of x (device f32 [n, d]):
+    (indices int32 [n, k], squared distances f32 [n, k] or None)."""
+    if x.dtype != torch.float32 or x.dim() != 2 or not x.is_cuda:
+        raise GLError(1, "x must be a device float32 [n, d] tensor")
+    x = x.contiguous()
+    n, d = x.shape
+    idx = torch.empty((n, k), dtype=torch.int32, device=x.device)
+    d2 = torch.empty((n, k), dtype=torch.float32, device=x.device) if with_distances else None
+    _check(load_library().gl_knn(_ptr(x), n, d, k, _ptr(idx), _ptr(d2) if d2 is not None else None,
+                                 _stream_handle(stream)))
+    return idx, d2
+
+
 class Server:
     """Continuous-batching server (gl_server_*): host requests in, host results out."""
 
@@ -317,7 +332,10 @@ class Server:
         self._meta = {}
 
     def submit(self, row_ptr, col, weight, labels, u0, *, eps, c, eta, precond, outer, sweeps,
-               delta0=1e-6, lambda_max=2.0, step_k=math.inf) -> int:
+               delta0=1e-6, lambda_max=2.0, step_k=math.inf, borrow=False) -> int:
+        """Queue a request.  borrow=True: the server reads the arrays in place
+        (GL_REQ_BORROW); they are kept referenced here until the result is
+        polled."""
         import numpy as np
         rp = np.ascontiguousarray(row_ptr, dtype=np.int64)
         cl = np.ascontiguousarray(col, dtype=np.int32)
@@ -329,10 +347,10 @@ class Server:
         n, K = U0.shape
         p = _Params(eps, c, eta, delta0, lambda_max, step_k, PRECONDS[precond], outer, sweeps, 0)
         req = _Request(n, cl.size, rp.ctypes.data, cl.ctypes.data, w.ctypes.data, lab.ctypes.data,
-                       U0.ctypes.data, K, 0, p)
+                       U0.ctypes.data, K, 1 if borrow else 0, p)
         t = ctypes.c_uint64()
         _check(load_library().gl_server_submit(self._h, ctypes.byref(req), ctypes.byref(t)))
-        self._meta[t.value] = (n, K, outer, sweeps)
+        self._meta[t.value] = (n, K, outer, sweeps, (rp, cl, w, lab, U0) if borrow else None)
         return t.value
 
     def poll(self, ticket: int, wait: bool = True):
@@ -340,7 +358,7 @@ class Server:
         import numpy as np
         if ticket not in self._meta:
             raise GLError(1, "unknown or consumed ticket")
-        n, K, T, m = self._meta[ticket]
+        n, K, T, m, _ = self._meta[ticket]
         U = np.empty((n, K), dtype=np.float32)
         lab = np.empty(n, dtype=np.int32)
         st = np.empty(stats_length(K, T, m), dtype=np.float64)

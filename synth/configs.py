@@ -170,16 +170,20 @@ def served_stream(count: int = 256, n_range=(1e4, 1e6), seed: int = 4):
             for i in range(count)]
 
 
-def served_problem(item: StreamItem, device="cpu") -> Problem:
+def served_problem(item: StreamItem, device="cpu", knn=None) -> Problem:
     """Request `item.index`: a K-component mixture in R^10 (means N(0, 9 I),
     unit covariance), self-tuning kNN graph, 2% labels, 20 x 4 damped Jacobi
-    with eps = 100, c = 11, eta = 100, bf16 storage."""
+    with eps = 100, c = 11, eta = 100, bf16 storage.
+
+    `knn(x, k)` may supply the neighbour indices [n, k] (int64 tensor) of the
+    float64 points x in place of the brute-force search here."""
     seed = 1000 + item.index
     r_data, r_lab, _ = _streams(seed)
     means = 3.0 * r_data.standard_normal((item.K, 10))
     x, comp = gaussian_mixture(item.n, means, 1.0, r_data)
     xt = torch.from_numpy(x).to(_dev(device))
-    g = self_tuning_graph(xt, knn_bruteforce(xt, item.knn_k))
+    nbr = knn(xt, item.knn_k) if knn is not None else knn_bruteforce(xt, item.knn_k)
+    g = self_tuning_graph(xt, nbr)
     del xt
     labels = random_labels(comp, 0.02, item.K, r_lab)
     return Problem(name=f"served-{item.index}", graph=g, K=item.K, labels=labels,

@@ -83,6 +83,15 @@ def test_null_arguments_rejected():
     assert lib.gl_assign_labels(10, 1, 1, None, None, None) == 1
     assert lib.gl_params_validate(None) == 1
     assert lib.gl_operator_destroy(None) == 0
+    assert lib.gl_knn(None, 100, 3, 5, None, None, None) == 1
+
+
+@pytest.mark.parametrize("n,d,k", [(100, 0, 5), (100, 65, 5), (100, 3, 0), (100, 3, 33), (5, 3, 5)])
+def test_knn_sizes_rejected(n, d, k):
+    # size checks come before any device access (dummy non-NULL pointers)
+    lib = gl.load_library()
+    dummy = ctypes.c_void_p(256)
+    assert lib.gl_knn(dummy, n, d, k, dummy, None, None) == 1
 
 
 def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):

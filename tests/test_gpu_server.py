@@ -261,3 +261,28 @@ def test_close_with_work_in_flight():
     t0 = time.time()
     srv.close()
     assert time.time() - t0 < 30.0
+
+
+def test_borrowed_request_equals_copied():
+    """GL_REQ_BORROW (arrays read in place, here from page-locked memory)
+    gives the same result as a copied request."""
+    p = served(3, 2500, 5, 14)
+    rp, col, w = p.graph.numpy()
+
+    def pinned(a):
+        t = torch.empty(a.shape, dtype=torch.from_numpy(a[:0].copy()).dtype, pin_memory=True)
+        t.numpy()[...] = a
+        return t.numpy()
+
+    arrs = [pinned(a) for a in (rp, col, w, np.asarray(p.labels, np.int32),
+                                np.asarray(p.u0, np.float32))]
+    srv = gl.Server(128 << 20, max_slots=4)
+    try:
+        tb = srv.submit(*arrs, borrow=True, **params(p))
+        tc = srv.submit(rp, col, w, p.labels, p.u0, **params(p))
+        rb, rc = srv.poll(tb), srv.poll(tc)
+    finally:
+        srv.close()
+    ref = alone(p, "bf16", "bf16")
+    assert_same_as_alone(rb, ref, "borrowed")
+    assert_same_as_alone(rc, ref, "copied")
