@@ -91,6 +91,11 @@ typedef enum gl_layout { GL_LAYOUT_AUTO = 0, GL_LAYOUT_DIRECT = 1, GL_LAYOUT_TIL
  *            It changes nothing in the result but the rounding order of the
  *            sums; a locality-preserving order (e.g. the Z-order of an image's
  *            pixel grid) lets the tile layout keep each block's gathers in LDS.
+ *            The operator is renumbered into this order: its sweeps read and
+ *            write the field in position order, and gl_solve,
+ *            gl_laplacian_apply, gl_power_max_eig and gl_time_sweeps move
+ *            their node-ordered inputs and outputs in and out once per call
+ *            (their workspaces grow accordingly).
  *   layout   gl_layout request.
  * Every degree d_i = sum_j w_ij must be > 0. */
 typedef struct gl_graph {
@@ -151,7 +156,7 @@ gl_status gl_operator_info(const gl_operator *op, int64_t *n, int64_t *nnz,
 
 /* Host: layout chosen (GL_LAYOUT_DIRECT or GL_LAYOUT_TILE), entries stored
  * (with padding), largest halo and total halo entries (tile only), and the
- * bytes of index/weight/order arrays one sweep streams.  Any pointer may be NULL. */
+ * bytes of index/weight arrays one sweep streams.  Any pointer may be NULL. */
 gl_status gl_operator_layout(const gl_operator *op, int32_t *layout, int64_t *stored_entries,
                              int32_t *halo_max, int64_t *halo_total, int64_t *stream_bytes);
 

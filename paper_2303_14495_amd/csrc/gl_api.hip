@@ -79,7 +79,7 @@ gl::RowLaunch row_launch(const gl_operator* op) {
     r.layout = op->layout;
     r.w = op->w;
     r.wdt = op->store_w;
-    r.order = op->order;
+    r.order = nullptr;  // an ordered operator is renumbered: kernels index positions
     r.n = op->n;
     if (op->layout == gl::LAYOUT_TILE) {
         r.trp = (const int32_t*)op->rp;
@@ -220,21 +220,41 @@ void free_op(gl_operator* op) {
 }
 
 template <typename TIN, typename TOUT>
-void launch_fill(gl_operator* op, const gl_graph* g, const int32_t* src, hipStream_t s) {
+void launch_fill(gl_operator* op, const gl_graph* g, const int32_t* src, const int32_t* pos_of, hipStream_t s) {
     const unsigned grid = (unsigned)((op->n + 255) / 256);
     hipLaunchKernelGGL((gl::fill_layout_kernel<TIN, TOUT>), dim3(grid), dim3(256), 0, s, op->n,
-                       (const int32_t*)op->rp, src, op->order, g->col_idx, static_cast<const TIN*>(g->weight),
-                       op->degree, static_cast<TOUT*>(op->w), op->col);
+                       (const int32_t*)op->rp, src, op->order, pos_of, g->col_idx,
+                       static_cast<const TIN*>(g->weight), op->degree, static_cast<TOUT*>(op->w), op->col);
 }
 
 template <typename TIN>
-void launch_fill_out(gl_operator* op, const gl_graph* g, const int32_t* src, hipStream_t s) {
+void launch_fill_out(gl_operator* op, const gl_graph* g, const int32_t* src, const int32_t* pos_of,
+                     hipStream_t s) {
     switch (op->store_w) {
-        case GL_F64: launch_fill<TIN, double>(op, g, src, s); break;
-        case GL_F32: launch_fill<TIN, float>(op, g, src, s); break;
-        case GL_BF16: launch_fill<TIN, gl::bf16>(op, g, src, s); break;
-        case GL_F16: launch_fill<TIN, gl::f16>(op, g, src, s); break;
+        case GL_F64: launch_fill<TIN, double>(op, g, src, pos_of, s); break;
+        case GL_F32: launch_fill<TIN, float>(op, g, src, pos_of, s); break;
+        case GL_BF16: launch_fill<TIN, gl::bf16>(op, g, src, pos_of, s); break;
+        case GL_F16: launch_fill<TIN, gl::f16>(op, g, src, pos_of, s); break;
     }
+}
+
+// Rows of `row_bytes` between node order (caller's arrays) and position order
+// (the renumbered operator's space): gather dst[p] = src[order[p]], or scatter
+// dst[order[p]] = src[p].
+hipError_t permute_rows(const gl_operator* op, size_t row_bytes, const void* src, void* dst, bool scatter,
+                        hipStream_t s) {
+    const int64_t n = op->n;
+    auto go = [&](auto unit) -> hipError_t {
+        typedef decltype(unit) W;
+        const int32_t words = (int32_t)(row_bytes / sizeof(W));
+        const unsigned grid = (unsigned)((n * words + 255) / 256);
+        hipLaunchKernelGGL(gl::permute_rows_kernel<W>, dim3(grid), dim3(256), 0, s, n, words, op->order,
+                           (const W*)src, (W*)dst, scatter ? 1 : 0);
+        return hipGetLastError();
+    };
+    if (row_bytes % 8 == 0) return go(uint64_t{});
+    if (row_bytes % 4 == 0) return go(uint32_t{});
+    return go(uint16_t{});
 }
 
 template <typename T>
@@ -432,10 +452,20 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
                 (op->layout == gl::LAYOUT_TILE ? (size_t)op->stored * 2 + (size_t)op->halo_total * 4 +
                                                      (size_t)(op->nblocks + 1) * 4
                                                : (size_t)op->stored * 4);
-    if (g->weight_dtype == GL_F64) launch_fill_out<double>(op, g, d_src, s);
-    else launch_fill_out<float>(op, g, d_src, s);
-    if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-        return cleanup_fail(GL_E_HIP, "weight normalization failed");
+    int32_t* d_pos_of = nullptr;
+    if (g->order && op->layout == gl::LAYOUT_DIRECT) {
+        std::vector<int32_t> pos_of(g->n);
+        for (int64_t p = 0; p < g->n; ++p) pos_of[h_order[p]] = (int32_t)p;
+        if (upload(&d_pos_of, pos_of, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
+            (void)hipFree(d_pos_of);
+            return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
+        }
+    }
+    if (g->weight_dtype == GL_F64) launch_fill_out<double>(op, g, d_src, d_pos_of, s);
+    else launch_fill_out<float>(op, g, d_src, d_pos_of, s);
+    const bool fill_ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
+    (void)hipFree(d_pos_of);
+    if (!fill_ok) return cleanup_fail(GL_E_HIP, "weight normalization failed");
     (void)hipFree(d_src);
     (void)hipFree(scratch);
     *out = op;
@@ -471,7 +501,7 @@ gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* st
     if (stream_bytes) {
         const int64_t rp = (op->n + 1) * (op->idx64 ? 8 : 4);
         const int64_t idx = tile ? op->stored * 2 + op->halo_total * 4 + (op->nblocks + 1) * 4 : op->stored * 4;
-        *stream_bytes = rp + idx + op->stored * (int64_t)dtype_size(op->store_w) + (op->order ? op->n * 4 : 0);
+        *stream_bytes = rp + idx + op->stored * (int64_t)dtype_size(op->store_w);
     }
     return GL_OK;
 }
@@ -485,14 +515,30 @@ gl_status gl_laplacian_apply(const gl_operator* op, int32_t K, gl_dtype dtype, c
     const size_t bytes = (size_t)op->n * K * dtype_size(dtype);
     const char *x = (const char*)X, *y = (const char*)Y;
     if (x < y + bytes && y < x + bytes) return fail(GL_E_INVALID_ARG, "X and Y overlap");
-    GL_HIP(launch_laplacian(dtype, K, row_launch(op), X, Y, (hipStream_t)stream), "laplacian launch");
+    hipStream_t s = (hipStream_t)stream;
+    if (!op->order) {
+        GL_HIP(launch_laplacian(dtype, K, row_launch(op), X, Y, s), "laplacian launch");
+        return GL_OK;
+    }
+    // renumbered operator: X -> position order, apply, scatter back (stream-ordered scratch)
+    const size_t row = (size_t)K * dtype_size(dtype);
+    void* tmp = nullptr;
+    GL_HIP(hipMallocAsync(&tmp, 2 * align256(bytes), s), "laplacian scratch");
+    char* tx = (char*)tmp;
+    char* ty = tx + align256(bytes);
+    hipError_t e = permute_rows(op, row, X, tx, false, s);
+    if (e == hipSuccess) e = launch_laplacian(dtype, K, row_launch(op), tx, ty, s);
+    if (e == hipSuccess) e = permute_rows(op, row, ty, Y, true, s);
+    const hipError_t ef = hipFreeAsync(tmp, s);
+    GL_HIP(e, "laplacian launch");
+    GL_HIP(ef, "laplacian scratch");
     return GL_OK;
 }
 
 gl_status gl_power_workspace_size(const gl_operator* op, size_t* bytes) {
     if (!op || !bytes) return fail(GL_E_INVALID_ARG, "operator and bytes must not be NULL");
     const gl::RowLaunch r = row_launch(op);
-    *bytes = 2 * align256((size_t)op->n * 4) + align256((size_t)2 * r.grid * 4) + 256;
+    *bytes = (op->order ? 3 : 2) * align256((size_t)op->n * 4) + align256((size_t)2 * r.grid * 4) + 256;
     return GL_OK;
 }
 
@@ -509,8 +555,9 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
     hipStream_t s = (hipStream_t)stream;
     const gl::RowLaunch r = row_launch(op);
     char* base = (char*)ws;
-    float* buf[2] = {(float*)base, (float*)(base + align256((size_t)op->n * 4))};
-    float* partials = (float*)(base + 2 * align256((size_t)op->n * 4));
+    const size_t vec = align256((size_t)op->n * 4);
+    float* buf[2] = {(float*)base, (float*)(base + vec)};
+    float* partials = (float*)(base + (op->order ? 3 : 2) * vec);
     char* tail = (char*)partials + align256((size_t)2 * r.grid * 4);
     float* scale = (float*)tail;
     double* sums = (double*)(tail + 64);
@@ -523,7 +570,7 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
             a.op.w = op->w;
             a.op.halo = op->halo;
             a.op.hp = op->hp;
-            a.op.order = op->order;
+            a.op.order = nullptr;
             a.op.n = op->n;
             a.x = x;
             a.y = y;
@@ -550,10 +597,10 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
         switch (op->store_w) {
 #define GL_POW(T)                                                                                   \
     if (op->idx64) {                                                                                \
-        gl::PowerArgs<T, int64_t> a{(const int64_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, op->order, geo, mode}; \
+        gl::PowerArgs<T, int64_t> a{(const int64_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, nullptr, geo, mode}; \
         hipLaunchKernelGGL((gl::power_kernel<T, int64_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
     } else {                                                                                        \
-        gl::PowerArgs<T, int32_t> a{(const int32_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, op->order, geo, mode}; \
+        gl::PowerArgs<T, int32_t> a{(const int32_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, nullptr, geo, mode}; \
         hipLaunchKernelGGL((gl::power_kernel<T, int32_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
     }
             case GL_F32: GL_POW(float) break;
@@ -569,6 +616,12 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
                            scale, sums);
         return hipGetLastError();
     };
+    if (op->order) {
+        // renumbered operator: iterate on x0 in position order
+        float* xp = (float*)(base + 2 * vec);
+        GL_HIP(permute_rows(op, 4, x0, xp, false, s), "power permute");
+        x0 = xp;
+    }
     // s_0 = 1/|x0| from the mode-1 pass over x0
     GL_HIP(pass(x0, nullptr, 1, nullptr), "power launch");
     GL_HIP(finalize(1), "power finalize");
@@ -598,7 +651,9 @@ gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype sto
     const gl::RowLaunch r = row_launch(op);
     const size_t field = align256((size_t)op->n * K * dtype_size(store_u));
     const size_t acc = store_u == GL_F64 ? 8 : 4;
-    *bytes = 2 * field + align256((size_t)2 * K * r.grid * acc);
+    // ordered operators keep all three field buffers and the labels in position order
+    *bytes = (op->order ? 3 * field + align256((size_t)op->n * 4) : 2 * field) +
+             align256((size_t)2 * K * r.grid * acc);
     return GL_OK;
 }
 
@@ -620,8 +675,20 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
     hipStream_t s = (hipStream_t)stream;
 
     const size_t field = align256((size_t)op->n * K * dtype_size(store_u));
+    const size_t row = (size_t)K * dtype_size(store_u);
     char* bufs[3] = {(char*)U, (char*)ws, (char*)ws + field};
     void* partials = (char*)ws + 2 * field;
+    if (op->order) {
+        // renumbered operator: u^0 and the labels move to position order once
+        bufs[0] = (char*)ws;
+        bufs[1] = (char*)ws + field;
+        bufs[2] = (char*)ws + 2 * field;
+        int32_t* lab_pos = (int32_t*)((char*)ws + 3 * field);
+        partials = (char*)lab_pos + align256((size_t)op->n * 4);
+        GL_HIP(permute_rows(op, row, U, bufs[0], false, s), "permute u0");
+        GL_HIP(permute_rows(op, 4, labels, lab_pos, false, s), "permute labels");
+        labels = lab_pos;
+    }
 
     gl::SweepLaunch L;
     L.r = row_launch(op);
@@ -677,7 +744,9 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
         GL_HIP(launch_sweep(store_u, K, L, s), "energy launch");
         GL_HIP(finalize(stats + (int64_t)T * K, nullptr), "stats launch");
     }
-    if (cur != 0)
+    if (op->order)
+        GL_HIP(permute_rows(op, row, bufs[cur], U, true, s), "result scatter");
+    else if (cur != 0)
         GL_HIP(copy_bytes(bufs[cur], U, (size_t)op->n * K * dtype_size(store_u), s), "result copy");
     return GL_OK;
 }
@@ -705,14 +774,25 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     L.labels = labels;
     L.partials = (char*)ws + 2 * field;
     L.energy = 0;
+    const void* ut = U;
+    if (op->order) {
+        // renumbered operator: time the sweep on position-ordered inputs
+        char* R = (char*)ws + 2 * field;
+        int32_t* lab_pos = (int32_t*)((char*)ws + 3 * field);
+        L.partials = (char*)lab_pos + align256((size_t)op->n * 4);
+        GL_HIP(permute_rows(op, (size_t)K * dtype_size(store_u), U, R, false, s), "permute u");
+        GL_HIP(permute_rows(op, 4, labels, lab_pos, false, s), "permute labels");
+        L.labels = lab_pos;
+        ut = R;
+    }
     const double g0 = precond_g(p.precond, 0.0, p), g1 = precond_g(p.precond, 1.0, p);
     const bool inf_k = std::isinf(p.step_k);
     const double coef[11] = {p.eps, p.c, p.eta, 1.0 / p.eps, 0.5 * p.eps, 0.25 / p.eps, 0.5 * p.eta,
                              1.0 / g0, 1.0 / g1, inf_k ? 0.0 : 1.0, inf_k ? 1.0 : p.step_k};
     std::memcpy(L.coef, coef, sizeof(coef));
-    L.ut = U;
+    L.ut = ut;
     // seed P with u^t so every timed sweep gathers finite values
-    GL_HIP(copy_bytes(U, P, (size_t)op->n * K * dtype_size(store_u), s), "copy");
+    GL_HIP(copy_bytes(ut, P, (size_t)op->n * K * dtype_size(store_u), s), "copy");
     hipEvent_t e0, e1;
     GL_HIP(hipEventCreate(&e0), "event");
     GL_HIP(hipEventCreate(&e1), "event");

@@ -244,6 +244,23 @@ static __global__ void copy_bytes_kernel(const u32x4* __restrict__ src, u32x4* _
     if (i < tail) dst_tail[i] = src_tail[i];
 }
 
+// Move whole rows between node order and position order:
+//   gather  (scatter = 0): dst[p] = src[order[p]]
+//   scatter (scatter = 1): dst[order[p]] = src[p]
+// Rows are `words` units of W (a row of K field values).
+template <typename W>
+__global__ void permute_rows_kernel(int64_t n, int32_t words, const int32_t* __restrict__ order,
+                                    const W* __restrict__ src, W* __restrict__ dst, int32_t scatter) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n * words) return;
+    const int64_t p = i / words, j = i - p * words;
+    const int64_t o = (int64_t)order[p] * words + j;
+    if (scatter)
+        dst[o] = src[i];
+    else
+        dst[i] = src[o];
+}
+
 template <typename TU>
 __global__ void labels_kernel(int64_t n, int32_t K, const TU* __restrict__ U, int32_t* __restrict__ out) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;

@@ -45,6 +45,14 @@ bool build_layout(int64_t n, const int64_t* rp, const int32_t* col, const int32_
                   bool require_tile, int32_t halo_limit, HostLayout& out, std::string& err) {
     auto node = [&](int64_t p) -> int64_t { return order ? (int64_t)order[p] : p; };
     out = HostLayout();
+    // With an order the operator works in position space: halo entries and
+    // columns name positions, so the field is read in processing order.
+    std::vector<int32_t> pos_of;
+    if (order) {
+        pos_of.resize(n);
+        for (int64_t p = 0; p < n; ++p) pos_of[order[p]] = (int32_t)p;
+    }
+    auto cpos = [&](int32_t j) -> int32_t { return order ? pos_of[j] : j; };
     if (try_tile) {
         const int64_t nb = (n + kLayoutRows - 1) / kLayoutRows;
         std::vector<int64_t> plen(n + 1, 0);
@@ -65,7 +73,7 @@ bool build_layout(int64_t n, const int64_t* rp, const int32_t* col, const int32_
                 const int64_t p0 = b * kLayoutRows, p1 = std::min(n, p0 + kLayoutRows);
                 for (int64_t p = p0; p < p1; ++p) {
                     const int64_t i = node(p);
-                    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) cols.push_back(col[e]);
+                    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) cols.push_back(cpos(col[e]));
                 }
                 std::sort(cols.begin(), cols.end());
                 cols.erase(std::unique(cols.begin(), cols.end()), cols.end());
@@ -102,7 +110,7 @@ bool build_layout(int64_t n, const int64_t* rp, const int32_t* col, const int32_
                         const int64_t i = node(p);
                         int64_t dst = plen[p];
                         for (int64_t e = rp[i]; e < rp[i + 1]; ++e, ++dst) {
-                            const auto it = std::lower_bound(h.begin(), h.end(), col[e]);
+                            const auto it = std::lower_bound(h.begin(), h.end(), cpos(col[e]));
                             out.lcol[dst] = (uint16_t)(it - h.begin());
                             out.src[dst] = (int32_t)e;
                         }

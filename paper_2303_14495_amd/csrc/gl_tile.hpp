@@ -349,12 +349,13 @@ __global__ __launch_bounds__(256) void tile_power_kernel(TilePowerArgs a) {
 // Fill the tile (or direct) weight array: entry e of position p takes the
 // normalized weight of source entry src[e] (w / sqrt(d_i d_j), i the node of p),
 // or 0 when src[e] < 0 (padding).  col_out (direct layout only) receives the
-// source column.
+// source column, mapped through pos_of (node -> position) when ordered.
 template <typename TIN, typename TOUT>
 __global__ void fill_layout_kernel(int64_t n, const int32_t* __restrict__ rp_out, const int32_t* __restrict__ src,
-                                   const int32_t* __restrict__ order, const int32_t* __restrict__ col,
-                                   const TIN* __restrict__ w, const double* __restrict__ d,
-                                   TOUT* __restrict__ w_out, int32_t* __restrict__ col_out) {
+                                   const int32_t* __restrict__ order, const int32_t* __restrict__ pos_of,
+                                   const int32_t* __restrict__ col, const TIN* __restrict__ w,
+                                   const double* __restrict__ d, TOUT* __restrict__ w_out,
+                                   int32_t* __restrict__ col_out) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int64_t i = order ? (int64_t)order[p] : p;
@@ -364,7 +365,7 @@ __global__ void fill_layout_kernel(int64_t n, const int32_t* __restrict__ rp_out
         if (s >= 0) {
             const int32_t j = col[s];
             w_out[e] = store_as<TOUT>::from((double)w[s] / sqrt(di * d[j]));
-            if (col_out) col_out[e] = j;
+            if (col_out) col_out[e] = pos_of ? pos_of[j] : j;
         } else {
             w_out[e] = store_as<TOUT>::from(0.0);
             if (col_out) col_out[e] = 0;
