@@ -758,7 +758,7 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     gl_status st = check_params(params);
     if (st != GL_OK) return st;
     if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
-    if (reps < 1) return fail(GL_E_INVALID_ARG, "reps must be >= 1");
+    if (reps < 1 || reps > 10000) return fail(GL_E_INVALID_ARG, "reps must lie in [1, 10000]");
     if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
     if (!aligned(U, 16) || !aligned(ws, 256)) return fail(GL_E_INVALID_ARG, "U / workspace misaligned");
     size_t need = 0;
@@ -793,22 +793,29 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     L.ut = ut;
     // seed P with u^t so every timed sweep gathers finite values
     GL_HIP(copy_bytes(ut, P, (size_t)op->n * K * dtype_size(store_u), s), "copy");
-    hipEvent_t e0, e1;
-    GL_HIP(hipEventCreate(&e0), "event");
-    GL_HIP(hipEventCreate(&e1), "event");
-    hipError_t err = hipEventRecord(e0, s);
+    // one event pair around every launch: the sum of the pairs' spans is the
+    // kernels' own time, without the gaps between back-to-back launches
+    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
+    hipError_t err = hipSuccess;
+    for (size_t i = 0; i < ev.size() && err == hipSuccess; ++i) err = hipEventCreate(&ev[i]);
     for (int i = 0; i < reps && err == hipSuccess; ++i) {
         L.vin = (i & 1) ? Q : P;
         L.vout = (i & 1) ? P : Q;
-        err = launch_sweep(store_u, K, L, s);
+        err = hipEventRecord(ev[2 * i], s);
+        if (err == hipSuccess) err = launch_sweep(store_u, K, L, s);
+        if (err == hipSuccess) err = hipEventRecord(ev[2 * i + 1], s);
     }
-    if (err == hipSuccess) err = hipEventRecord(e1, s);
-    if (err == hipSuccess) err = hipEventSynchronize(e1);
-    float ms = 0.f;
-    if (err == hipSuccess) err = hipEventElapsedTime(&ms, e0, e1);
-    (void)hipEventDestroy(e0);
-    (void)hipEventDestroy(e1);
+    if (err == hipSuccess) err = hipEventSynchronize(ev.back());
+    double total = 0.0;
+    for (int i = 0; i < reps && err == hipSuccess; ++i) {
+        float ms = 0.f;
+        err = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
+        total += ms;
+    }
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
     GL_HIP(err, "timed sweeps");
+    const double ms = total;
     *avg_ms = (double)ms / reps;
     return GL_OK;
 }

@@ -10,11 +10,12 @@
 //
 // Kernel plan (one 256-thread workgroup per block, no dependent global loads
 // beyond two levels):
-//   1. row offsets of the block -> LDS; halo ids and own-row ids -> registers;
-//   2. issue every index/weight vector load of the block's rows, the gathers of
-//      the halo rows of V and the own-row inputs of the epilogue;
-//   3. halo rows -> LDS, barrier, products from LDS, butterfly over the 4 lanes
-//      of each row (fixed order), epilogue on lanes q = column (mod 4).
+//   1. halo ids and each lane group's row offsets -> registers;
+//   2. issue the gathers of the halo rows of V, then the first 4-entry chunk of
+//      every row's index/weight stream;
+//   3. halo rows -> LDS, barrier, own-row inputs of the epilogue, products from
+//      LDS, butterfly over the 4 lanes of each row (fixed order), epilogue on
+//      lanes q = column (mod 4).
 // Gathers thus hit LDS instead of the vector L1, and the index stream shrinks
 // from 4 to 2 bytes per nonzero.
 #pragma once
@@ -27,7 +28,13 @@ namespace gl {
 
 constexpr int kTileRows = 256;   // positions per block
 constexpr int kTileG = 4;        // lanes per row
-constexpr int kTileUnr = 2;      // 4-entry chunks per lane loaded up front
+// 4-entry chunks per lane loaded before the halo is staged: one for 2-byte
+// weights (fewer live registers, more resident blocks), two for 4- and 8-byte
+// weights; with 2-byte weights the second chunk is loaded right after the
+// halo rows have gone to LDS (their registers are free by then), close enough
+// to the first to find its cache lines still in L2.
+template <typename TW> constexpr int tile_unr() { return sizeof(TW) == 2 ? 1 : 2; }
+template <typename TW> constexpr int tile_late() { return sizeof(TW) == 2 ? 1 : 0; }
 constexpr int kTileRPT = 256 / kTileG;            // rows per pass of the block
 constexpr int kTilePasses = kTileRows / kTileRPT;  // 4
 constexpr int kTileHPT = 4;      // halo entries per thread held in registers
@@ -68,46 +75,48 @@ struct TileRows {
     bool ok[kTilePasses];
 };
 
-// Phases 1-3 for one block.  `prefetch(rows)` runs after the global loads are
-// issued and before the halo is stored to LDS, so the caller's own-row loads
-// overlap with the gathers; `finish(tt, zs)` receives the completed sums of
+// Phases 1-3 for one block.  Order of the loads: halo ids and row offsets,
+// then the gathers of the halo rows of V (so that they return first and the
+// halo can be staged in LDS while the index/weight stream is still in flight),
+// then the first chunk of every row.  `prefetch(rows)` runs after the barrier
+// (the caller's own-row loads); `finish(tt, zs)` receives the completed sums of
 // pass tt for the columns q, q + 4, ... that lane q finishes.
 template <int K, typename TW, typename TU, typename A, typename Prefetch, typename Finish>
-__device__ __forceinline__ void tile_products(const TileOp& op, const TU* __restrict__ V, int64_t b,
-                                              int32_t* s_rp, A* hv, TileRows& rows, Prefetch&& prefetch,
-                                              Finish&& finish) {
+__device__ __forceinline__ void tile_products(const TileOp& op, const TU* __restrict__ V, int64_t b, A* hv,
+                                              TileRows& rows, Prefetch&& prefetch, Finish&& finish) {
     typedef typename wvec4<TW>::type WV;
     const TW* __restrict__ w = static_cast<const TW*>(op.w);
     const int t = threadIdx.x;
     const int64_t n = op.n;
     const int64_t row0 = b * kTileRows;
-    {
-        const int64_t r = row0 + t;
-        s_rp[t] = op.rp[r < n ? r : n];
-        if (t == 0) s_rp[kTileRows] = op.rp[(row0 + kTileRows) < n ? row0 + kTileRows : n];
-    }
+    const int q = t & (kTileG - 1), grp = t / kTileG;
     const int32_t hb = op.hp[b], he = op.hp[b + 1];
     int32_t hid[kTileHPT];
 #pragma unroll
     for (int i = 0; i < kTileHPT; ++i) hid[i] = (hb + t + 256 * i < he) ? op.halo[hb + t + 256 * i] : -1;
-    const int q = t & (kTileG - 1), grp = t / kTileG;
+    int32_t beg[kTilePasses], end[kTilePasses];
 #pragma unroll
     for (int tt = 0; tt < kTilePasses; ++tt) {
         const int64_t p = row0 + tt * kTileRPT + grp;
+        const int64_t p0 = p < n ? p : n, p1 = p + 1 < n ? p + 1 : n;
+        beg[tt] = op.rp[p0];
+        end[tt] = op.rp[p1];
         rows.ok[tt] = p < n;
         rows.node[tt] = rows.ok[tt] ? (op.order ? (int64_t)op.order[p] : p) : 0;
     }
-    __syncthreads();  // s_rp visible
+    A hvr[kTileHPT][K];
+#pragma unroll
+    for (int i = 0; i < kTileHPT; ++i)
+        if (hid[i] >= 0) load_row<K>(V + (int64_t)hid[i] * K, hvr[i]);
+    constexpr int kTileUnr = tile_unr<TW>();
     u32x2 lr[kTilePasses][kTileUnr];
     WV wr[kTilePasses][kTileUnr];
 #pragma unroll
     for (int tt = 0; tt < kTilePasses; ++tt) {
-        const int lrow = tt * kTileRPT + grp;
-        const int32_t beg = s_rp[lrow], end = s_rp[lrow + 1];
 #pragma unroll
         for (int u = 0; u < kTileUnr; ++u) {
-            const int32_t pp = beg + 4 * q + 4 * kTileG * u;
-            if (pp < end) {
+            const int32_t pp = beg[tt] + 4 * q + 4 * kTileG * u;
+            if (pp < end[tt]) {
                 lr[tt][u] = *reinterpret_cast<const u32x2*>(op.lcol + pp);
                 wr[tt][u] = *reinterpret_cast<const WV*>(w + pp);
             } else {
@@ -115,11 +124,6 @@ __device__ __forceinline__ void tile_products(const TileOp& op, const TU* __rest
             }
         }
     }
-    A hvr[kTileHPT][K];
-#pragma unroll
-    for (int i = 0; i < kTileHPT; ++i)
-        if (hid[i] >= 0) load_row<K>(V + (int64_t)hid[i] * K, hvr[i]);
-    prefetch(rows);
 #pragma unroll
     for (int i = 0; i < kTileHPT; ++i) {
         if (hid[i] >= 0) {
@@ -133,7 +137,24 @@ __device__ __forceinline__ void tile_products(const TileOp& op, const TU* __rest
 #pragma unroll
         for (int k = 0; k < K; ++k) hv[idx * K + k] = v[k];
     }
+    constexpr int kTileLate = tile_late<TW>();
+    u32x2 lr2[kTilePasses][kTileLate > 0 ? kTileLate : 1];
+    WV wr2[kTilePasses][kTileLate > 0 ? kTileLate : 1];
+#pragma unroll
+    for (int tt = 0; tt < kTilePasses; ++tt) {
+#pragma unroll
+        for (int u = 0; u < kTileLate; ++u) {
+            const int32_t pp = beg[tt] + 4 * q + 4 * kTileG * (kTileUnr + u);
+            if (pp < end[tt]) {
+                lr2[tt][u] = *reinterpret_cast<const u32x2*>(op.lcol + pp);
+                wr2[tt][u] = *reinterpret_cast<const WV*>(w + pp);
+            } else {
+                lr2[tt][u] = u32x2{0xFFFFFFFFu, 0xFFFFFFFFu};
+            }
+        }
+    }
     __syncthreads();  // halo visible
+    prefetch(rows);
     static_for<0, kTilePasses>([&](auto TT) {
         constexpr int tt = decltype(TT)::value;
         A z[K];
@@ -154,10 +175,24 @@ __device__ __forceinline__ void tile_products(const TileOp& op, const TU* __rest
                 }
             }
         }
-        // rows longer than the prefetched part (rare)
-        const int lrow = tt * kTileRPT + grp;
-        const int32_t end = s_rp[lrow + 1];
-        for (int32_t pp = s_rp[lrow] + 4 * q + 4 * kTileG * kTileUnr; pp < end; pp += 4 * kTileG) {
+#pragma unroll
+        for (int u = 0; u < kTileLate; ++u) {
+            uint16_t li[4];
+            TW wi[4];
+            __builtin_memcpy(li, &lr2[tt][u], 8);
+            __builtin_memcpy(wi, &wr2[tt][u], sizeof(WV));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) {
+                if (li[e] != 0xFFFFu) {
+                    const A we = cvt<A>(wi[e]);
+#pragma unroll
+                    for (int k = 0; k < K; ++k) z[k] += we * hv[(int32_t)li[e] * K + k];
+                }
+            }
+        }
+        // the rest of the row, one 4-entry chunk per lane at a time
+        for (int32_t pp = beg[tt] + 4 * q + 4 * kTileG * (kTileUnr + kTileLate); pp < end[tt];
+             pp += 4 * kTileG) {
             const u32x2 l2 = *reinterpret_cast<const u32x2*>(op.lcol + pp);
             const WV w2 = *reinterpret_cast<const WV*>(w + pp);
             uint16_t li[4];
@@ -211,7 +246,6 @@ template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(256) void tile_sweep_kernel(TileSweepArgs<TU, typename acc_of<TU>::type> a) {
     typedef typename acc_of<TU>::type A;
     constexpr int CPL = (K + kTileG - 1) / kTileG;
-    __shared__ int32_t s_rp[kTileRows + 1];
     extern __shared__ unsigned char smem_raw[];
     A* hv = reinterpret_cast<A*>(smem_raw);
     const int64_t b = blockIdx.x;
@@ -262,7 +296,7 @@ __global__ __launch_bounds__(256) void tile_sweep_kernel(TileSweepArgs<TU, typen
             }
         }
     };
-    tile_products<K, TW, TU, A>(a.op, a.vin, b, s_rp, hv, rows, prefetch, finish);
+    tile_products<K, TW, TU, A>(a.op, a.vin, b, hv, rows, prefetch, finish);
     if (a.partials) block_stats<K, CPL>(e_acc, r_acc, kTileG, a.partials, (int64_t)gridDim.x, b);
 }
 
@@ -277,7 +311,6 @@ template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(256) void tile_laplacian_kernel(TileLapArgs<TU> a) {
     typedef typename acc_of<TU>::type A;
     constexpr int CPL = (K + kTileG - 1) / kTileG;
-    __shared__ int32_t s_rp[kTileRows + 1];
     extern __shared__ unsigned char smem_raw[];
     A* hv = reinterpret_cast<A*>(smem_raw);
     const int q = threadIdx.x & (kTileG - 1);
@@ -301,7 +334,7 @@ __global__ __launch_bounds__(256) void tile_laplacian_kernel(TileLapArgs<TU> a) 
             if (k < K) a.y[rows.node[tt] * K + k] = store_as<TU>::from(xx[tt][c] - zs[c]);
         }
     };
-    tile_products<K, TW, TU, A>(a.op, a.x, (int64_t)blockIdx.x, s_rp, hv, rows, prefetch, finish);
+    tile_products<K, TW, TU, A>(a.op, a.x, (int64_t)blockIdx.x, hv, rows, prefetch, finish);
 }
 
 // Power-method pass on the tile layout (float vectors; see power_kernel).
@@ -316,7 +349,6 @@ struct TilePowerArgs {
 
 template <typename TW>
 __global__ __launch_bounds__(256) void tile_power_kernel(TilePowerArgs a) {
-    __shared__ int32_t s_rp[kTileRows + 1];
     extern __shared__ unsigned char smem_raw[];
     float* hv = reinterpret_cast<float*>(smem_raw);
     const int q = threadIdx.x & (kTileG - 1);
@@ -341,7 +373,7 @@ __global__ __launch_bounds__(256) void tile_power_kernel(TilePowerArgs a) {
             p1 += xx[tt] * xx[tt];
         }
     };
-    tile_products<1, TW, float, float>(a.op, a.x, (int64_t)blockIdx.x, s_rp, hv, rows, prefetch, finish);
+    tile_products<1, TW, float, float>(a.op, a.x, (int64_t)blockIdx.x, hv, rows, prefetch, finish);
     float e[1] = {p0}, r[1] = {p1};
     block_stats<1, 1>(e, r, kTileG, a.partials, (int64_t)gridDim.x, (int64_t)blockIdx.x);
 }
