@@ -18,6 +18,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 SRC = os.path.join(_HERE, "gl_oracle.c")
 LIB = os.path.join(_HERE, "libgl_oracle.so")
 _PRECOND = {"damped_jacobi": 0, "perturbed_jacobi": 1, "richardson": 2}
+_LAPLACIAN = {"normalized": 0, "unnormalized": 1}
 _lib = None
 
 
@@ -39,11 +40,11 @@ def load():
     P = ctypes.c_void_p
     i64, i32, f64 = ctypes.c_int64, ctypes.c_int32, ctypes.c_double
     lib.glo_solve.argtypes = [i64, P, P, P, i32, P, P, f64, f64, f64, i32, i32, i32,
-                              f64, f64, f64, P, P]
+                              f64, f64, f64, P, P, i32]
     lib.glo_solve.restype = ctypes.c_int
-    lib.glo_power.argtypes = [i64, P, P, P, P, i32, P, P]
+    lib.glo_power.argtypes = [i64, P, P, P, P, i32, P, P, i32]
     lib.glo_power.restype = ctypes.c_int
-    lib.glo_laplacian_apply.argtypes = [i64, P, P, P, i32, P, P]
+    lib.glo_laplacian_apply.argtypes = [i64, P, P, P, i32, P, P, i32]
     lib.glo_laplacian_apply.restype = ctypes.c_int
     lib.glo_num_threads.argtypes = []
     lib.glo_num_threads.restype = ctypes.c_int
@@ -66,7 +67,8 @@ def num_threads() -> int:
 
 
 def dca_solve(n, row_ptr, col, w, labels, u0, *, eps, c, eta, precond, outer, sweeps,
-              delta0=1e-6, lambda_max=2.0, step_k=math.inf, record=True):
+              delta0=1e-6, lambda_max=2.0, step_k=math.inf, record=True,
+              laplacian="normalized"):
     """Same contract as gl_oracle.dca_solve."""
     lib = load()
     rp, cl, ww = _csr(row_ptr, col, w)
@@ -79,30 +81,33 @@ def dca_solve(n, row_ptr, col, w, labels, u0, *, eps, c, eta, precond, outer, sw
     rs = np.zeros((outer, sweeps, K)) if record else None
     rc = lib.glo_solve(n, _ptr(rp), _ptr(cl), _ptr(ww), K, _ptr(lab), _ptr(U),
                        eps, c, eta, _PRECOND[precond], outer, sweeps, delta0, lambda_max,
-                       step_k, _ptr(en) if record else None, _ptr(rs) if record else None)
+                       step_k, _ptr(en) if record else None, _ptr(rs) if record else None,
+                       _LAPLACIAN[laplacian])
     if rc != 0:
         raise MemoryError("C oracle allocation failed")
     return U, en, rs
 
 
-def power_max_eig(n, row_ptr, col, w, x0, iters=150):
+def power_max_eig(n, row_ptr, col, w, x0, iters=150, laplacian="normalized"):
     lib = load()
     rp, cl, ww = _csr(row_ptr, col, w)
     x = np.ascontiguousarray(x0, dtype=np.float64).reshape(-1)
     rq = np.zeros(1)
     lh = np.zeros(1)
-    if lib.glo_power(n, _ptr(rp), _ptr(cl), _ptr(ww), _ptr(x), iters, _ptr(rq), _ptr(lh)):
+    if lib.glo_power(n, _ptr(rp), _ptr(cl), _ptr(ww), _ptr(x), iters, _ptr(rq), _ptr(lh),
+                     _LAPLACIAN[laplacian]):
         raise MemoryError("C oracle allocation failed")
     return float(rq[0]), float(lh[0])
 
 
-def laplacian_apply(n, row_ptr, col, w, X):
+def laplacian_apply(n, row_ptr, col, w, X, laplacian="normalized"):
     lib = load()
     rp, cl, ww = _csr(row_ptr, col, w)
     X = np.ascontiguousarray(X, dtype=np.float64)
     if X.ndim == 1:
         X = X[:, None].copy()
     Y = np.empty_like(X)
-    if lib.glo_laplacian_apply(n, _ptr(rp), _ptr(cl), _ptr(ww), X.shape[1], _ptr(X), _ptr(Y)):
+    if lib.glo_laplacian_apply(n, _ptr(rp), _ptr(cl), _ptr(ww), X.shape[1], _ptr(X), _ptr(Y),
+                               _LAPLACIAN[laplacian]):
         raise MemoryError("C oracle allocation failed")
     return Y

@@ -6,14 +6,17 @@
  * baseline of the benchmark; never by the product library, and it shares no
  * code with it.  The algorithm and its readings are those of gl_oracle.py:
  *
- *   normalized weights   what_ij = w_ij / sqrt(d_i d_j), d_i = sum_j w_ij
- *                        (Section 2.2, L_s = I - D^{-1/2} W D^{-1/2})
+ *   Laplacian            written as diag(dd) - A (Section 2.2):
+ *                        L_s = I - D^{-1/2} W D^{-1/2}: A_ij = w_ij / sqrt(d_i d_j), dd = 1;
+ *                        L   = D - W:                   A = W,                      dd = d;
+ *                        d_i = sum_j w_ij
  *   DCA right-hand side  b = c u - (u^3 - u)/eps + eta Lambda y      (Prop. 1)
- *   operator             T v = eps (v - What v) + eta Lambda v + c v  (Section 3)
+ *   operator             T v = eps (dd v - A v) + eta Lambda v + c v  (Section 3)
  *   sweep                v <- v + (b - T v) / g, all old values       (Section 3.1)
  *                        finite step k: r = (u + k b) - (v + k T v)   (Lemma 1)
- *   preconditioners      g from G_Jd,s / G_Jp,s / G_R,s or their k versions
- *   energy               (eps/2) u.L_s u + sum (u^2-1)^2/(4 eps)
+ *   preconditioners      g from G_Jd,s / G_Jp,s / G_R,s (L_s) or G_Jd / G_Jp / G_R (L),
+ *                        or their step-size-k versions                (Section 3.1)
+ *   energy               (eps/2) u.L u + sum (u^2-1)^2/(4 eps)
  *                        + (eta/2) sum Lambda (u - y)^2               (Section 2.1)
  *
  * Rows are split over OpenMP threads; every row is summed in CSR order.
@@ -28,24 +31,34 @@
 
 enum { GLO_DAMPED_JACOBI = 0, GLO_PERTURBED_JACOBI = 1, GLO_RICHARDSON = 2 };
 
-static double *normalized(int64_t n, const int64_t *rp, const int32_t *col, const double *w)
+/* The off-diagonal part A and the diagonal dd of the chosen Laplacian; both
+   arrays are malloc'ed (freed by the caller). */
+static int operator_parts(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
+                          int32_t unnormalized, double **A_out, double **dd_out)
 {
     int64_t nnz = rp[n];
     double *d = (double *)malloc(sizeof(double) * (size_t)(n > 0 ? n : 1));
-    double *wh = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
-    if (!d || !wh) { free(d); free(wh); return NULL; }
+    double *A = (double *)malloc(sizeof(double) * (size_t)(nnz > 0 ? nnz : 1));
+    if (!d || !A) { free(d); free(A); return 1; }
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         double s = 0.0;
         for (int64_t p = rp[i]; p < rp[i + 1]; p++) s += w[p];
         d[i] = s;
     }
+    if (unnormalized) {
+        memcpy(A, w, sizeof(double) * (size_t)nnz);
+    } else {
 #pragma omp parallel for schedule(static)
-    for (int64_t i = 0; i < n; i++)
-        for (int64_t p = rp[i]; p < rp[i + 1]; p++)
-            wh[p] = w[p] / sqrt(d[i] * d[col[p]]);
-    free(d);
-    return wh;
+        for (int64_t i = 0; i < n; i++)
+            for (int64_t p = rp[i]; p < rp[i + 1]; p++)
+                A[p] = w[p] / sqrt(d[i] * d[col[p]]);
+#pragma omp parallel for schedule(static)
+        for (int64_t i = 0; i < n; i++) d[i] = 1.0;
+    }
+    *A_out = A;
+    *dd_out = d;
+    return 0;
 }
 
 /* y_ik of node i (0 when unlabelled; K == 1: class 1 -> +1, class 0 -> -1). */
@@ -56,40 +69,43 @@ static double target(int32_t label, int32_t K, int32_t k)
     return label == k ? 1.0 : -1.0;
 }
 
-static double gdiag(int kind, double lam, double eps, double c, double eta,
+/* Diagonal preconditioner of node i with diagonal dd_i of the Laplacian
+   (dd_i = 1 for L_s: G_Jd,s, G_Jp,s, G_R,s and their k versions; dd_i = d_i
+   for L: G_Jd, G_Jp, G_R and their k versions; Section 3.1). */
+static double gdiag(int kind, double lam, double dd, double eps, double c, double eta,
                     double delta0, double lmax, double k)
 {
     double el = eta * lam;
     if (isinf(k)) {
-        if (kind == GLO_DAMPED_JACOBI) return 2.0 * (eps + el + c);
-        if (kind == GLO_PERTURBED_JACOBI) return 2.0 * eps + el + c + delta0;
+        if (kind == GLO_DAMPED_JACOBI) return 2.0 * (eps * dd + el + c);
+        if (kind == GLO_PERTURBED_JACOBI) return 2.0 * eps * dd + el + c + delta0;
         return eps * lmax + el + c + delta0;
     }
-    if (kind == GLO_DAMPED_JACOBI) return 2.0 * (1.0 + k * (eps + c) + k * el);
-    if (kind == GLO_PERTURBED_JACOBI) return (2.0 * k * eps + 1.0) + k * (el + c) + delta0;
+    if (kind == GLO_DAMPED_JACOBI) return 2.0 * (1.0 + k * (eps * dd + el + c));
+    if (kind == GLO_PERTURBED_JACOBI) return 1.0 + k * (2.0 * eps * dd + el + c) + delta0;
     return 1.0 + k * (eps * lmax + el + c) + delta0;
 }
 
-/* Y = L_s X for n x K row-major X. */
+/* Y = L_s X or L X for n x K row-major X. */
 int glo_laplacian_apply(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
-                        int32_t K, const double *X, double *Y)
+                        int32_t K, const double *X, double *Y, int32_t unnormalized)
 {
-    double *wh = normalized(n, rp, col, w);
-    if (!wh) return 1;
+    double *A, *dd;
+    if (operator_parts(n, rp, col, w, unnormalized, &A, &dd)) return 1;
 #pragma omp parallel for schedule(static)
     for (int64_t i = 0; i < n; i++) {
         for (int32_t k = 0; k < K; k++) {
             double z = 0.0;
-            for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * X[(int64_t)col[p] * K + k];
-            Y[i * K + k] = X[i * K + k] - z;
+            for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += A[p] * X[(int64_t)col[p] * K + k];
+            Y[i * K + k] = dd[i] * X[i * K + k] - z;
         }
     }
-    free(wh);
+    free(A); free(dd);
     return 0;
 }
 
 static void energy_cols(int64_t n, const int64_t *rp, const int32_t *col, const double *wh,
-                        int32_t K, const int32_t *labels, const double *U,
+                        const double *dd, int32_t K, const int32_t *labels, const double *U,
                         double eps, double eta, double *out)
 {
     double *lap = (double *)calloc((size_t)K, sizeof(double));
@@ -100,7 +116,7 @@ static void energy_cols(int64_t n, const int64_t *rp, const int32_t *col, const 
         for (int32_t k = 0; k < K; k++) {
             double u = U[i * K + k], z = 0.0;
             for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * U[(int64_t)col[p] * K + k];
-            lap[k] += u * (u - z);
+            lap[k] += u * (dd[i] * u - z);
             well[k] += (u * u - 1.0) * (u * u - 1.0);
             if (labels[i] >= 0) {
                 double e = u - target(labels[i], K, k);
@@ -121,21 +137,22 @@ int glo_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
               int32_t K, const int32_t *labels, double *U,
               double eps, double c, double eta, int32_t precond,
               int32_t outer, int32_t sweeps, double delta0, double lambda_max, double step_k,
-              double *energies, double *res_sq)
+              double *energies, double *res_sq, int32_t unnormalized)
 {
-    double *wh = normalized(n, rp, col, w);
+    double *wh = NULL, *dd = NULL;
+    if (operator_parts(n, rp, col, w, unnormalized, &wh, &dd)) return 1;
     size_t cells = (size_t)n * (size_t)K;
     double *b = (double *)malloc(sizeof(double) * (cells ? cells : 1));
     double *V = (double *)malloc(sizeof(double) * (cells ? cells : 1));
     double *Vn = (double *)malloc(sizeof(double) * (cells ? cells : 1));
     double *rs = (double *)calloc((size_t)K, sizeof(double));
-    if (!wh || !b || !V || !Vn || !rs) {
-        free(wh); free(b); free(V); free(Vn); free(rs);
+    if (!b || !V || !Vn || !rs) {
+        free(wh); free(dd); free(b); free(V); free(Vn); free(rs);
         return 1;
     }
     int finite_k = !isinf(step_k);
     for (int32_t t = 0; t < outer; t++) {
-        if (energies) energy_cols(n, rp, col, wh, K, labels, U, eps, eta, energies + (int64_t)t * K);
+        if (energies) energy_cols(n, rp, col, wh, dd, K, labels, U, eps, eta, energies + (int64_t)t * K);
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; i++) {
             double lam = labels[i] >= 0 ? 1.0 : 0.0;
@@ -150,12 +167,12 @@ int glo_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
 #pragma omp parallel for schedule(static) reduction(+ : rs[:K])
             for (int64_t i = 0; i < n; i++) {
                 double lam = labels[i] >= 0 ? 1.0 : 0.0;
-                double g = gdiag(precond, lam, eps, c, eta, delta0, lambda_max, step_k);
+                double g = gdiag(precond, lam, dd[i], eps, c, eta, delta0, lambda_max, step_k);
                 for (int32_t k = 0; k < K; k++) {
                     double z = 0.0;
                     for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * V[(int64_t)col[p] * K + k];
                     double v = V[i * K + k];
-                    double Tv = eps * (v - z) + eta * lam * v + c * v;
+                    double Tv = eps * (dd[i] * v - z) + eta * lam * v + c * v;
                     double r = finite_k ? (U[i * K + k] + step_k * b[i * K + k]) - (v + step_k * Tv)
                                         : b[i * K + k] - Tv;
                     rs[k] += r * r;
@@ -168,20 +185,23 @@ int glo_solve(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
         }
         memcpy(U, V, sizeof(double) * cells);
     }
-    if (energies) energy_cols(n, rp, col, wh, K, labels, U, eps, eta, energies + (int64_t)outer * K);
-    free(wh); free(b); free(V); free(Vn); free(rs);
+    if (energies) energy_cols(n, rp, col, wh, dd, K, labels, U, eps, eta, energies + (int64_t)outer * K);
+    free(wh); free(dd); free(b); free(V); free(Vn); free(rs);
     return 0;
 }
 
-/* Power method on L_s from x0 (n); writes the Rayleigh quotient of the final
-   unit vector to *rq and min(2, 1.01 rq) to *lambda_hat. */
+/* Power method on L_s (or L) from x0 (n); writes the Rayleigh quotient of the
+   final unit vector to *rq and min(2 max dd, 1.01 rq) to *lambda_hat. */
 int glo_power(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
-              const double *x0, int32_t iters, double *rq, double *lambda_hat)
+              const double *x0, int32_t iters, double *rq, double *lambda_hat, int32_t unnormalized)
 {
-    double *wh = normalized(n, rp, col, w);
+    double *wh = NULL, *dd = NULL;
+    if (operator_parts(n, rp, col, w, unnormalized, &wh, &dd)) return 1;
     double *x = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
     double *y = (double *)malloc(sizeof(double) * (size_t)(n ? n : 1));
-    if (!wh || !x || !y) { free(wh); free(x); free(y); return 1; }
+    if (!x || !y) { free(wh); free(dd); free(x); free(y); return 1; }
+    double ddmax = 0.0;
+    for (int64_t i = 0; i < n; i++) ddmax = dd[i] > ddmax ? dd[i] : ddmax;
     double nrm = 0.0;
     for (int64_t i = 0; i < n; i++) nrm += x0[i] * x0[i];
     nrm = sqrt(nrm);
@@ -192,7 +212,7 @@ int glo_power(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
         for (int64_t i = 0; i < n; i++) {
             double z = 0.0;
             for (int64_t p = rp[i]; p < rp[i + 1]; p++) z += wh[p] * x[col[p]];
-            y[i] = x[i] - z;
+            y[i] = dd[i] * x[i] - z;
             ss += y[i] * y[i];
             xy += x[i] * y[i];
         }
@@ -204,8 +224,8 @@ int glo_power(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; i++) x[i] = y[i] * inv;
     }
-    *lambda_hat = fmin(2.0, 1.01 * *rq);
-    free(wh); free(x); free(y);
+    *lambda_hat = fmin(2.0 * ddmax, 1.01 * *rq);
+    free(wh); free(dd); free(x); free(y);
     return 0;
 }
 

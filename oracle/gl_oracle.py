@@ -18,7 +18,12 @@ notes of the repository):
     uses one-vs-rest +-1 columns with a double well per column;
     Lambda_i = 1 iff node i is labelled;
   * Richardson: lambda_hat = min(2, 1.01 * Rayleigh quotient) after the power
-    iterations, feasible because 2I >= L_s (Prop. 3).
+    iterations, feasible because 2I >= L_s (Prop. 3); for the unnormalized L
+    the cap is 2 max_i d_i, since L <= 2D (Prop. 3);
+  * the unnormalized Laplacian L = D - W (Section 2.2) replaces L_s in the
+    energy and in T = eps L + eta Lambda + c I, with the D-dependent
+    preconditioners G_Jd, G_Jp, G_R and their step-size-k versions of
+    Section 3.1.
 """
 
 from __future__ import annotations
@@ -29,6 +34,7 @@ import numpy as np
 import scipy.sparse as sp
 
 PRECONDS = ("damped_jacobi", "perturbed_jacobi", "richardson")
+LAPLACIANS = ("normalized", "unnormalized")
 
 
 # ---------------------------------------------------------------------------
@@ -57,11 +63,39 @@ def normalized_adjacency(n, row_ptr, col, w):
     return sp.csr_matrix((wh, col.astype(np.int64), row_ptr.astype(np.int64)), shape=(n, n))
 
 
-def laplacian_apply(n, row_ptr, col, w, X):
-    """L_s X = X - D^{-1/2} W D^{-1/2} X (Section 2.2), X is n x K."""
-    A = normalized_adjacency(n, row_ptr, col, w)
+def operator_parts(n, row_ptr, col, w, laplacian="normalized"):
+    """(A, dd) with the Laplacian written as diag(dd) - A (Section 2.2):
+    normalized   L_s = I - D^{-1/2} W D^{-1/2}:  A = D^{-1/2} W D^{-1/2}, dd = 1;
+    unnormalized L   = D - W:                    A = W,                 dd = d."""
+    if laplacian == "normalized":
+        return normalized_adjacency(n, row_ptr, col, w), np.ones(n)
+    if laplacian == "unnormalized":
+        d = degrees(n, row_ptr, col, w)
+        if np.any(d <= 0):
+            raise ValueError("every degree must be positive")
+        W = sp.csr_matrix((np.asarray(w, dtype=np.float64), col.astype(np.int64),
+                           row_ptr.astype(np.int64)), shape=(n, n))
+        return W, d
+    raise ValueError(f"unknown laplacian {laplacian}")
+
+
+def laplacian_apply(n, row_ptr, col, w, X, laplacian="normalized"):
+    """L_s X = X - D^{-1/2} W D^{-1/2} X, or L X = D X - W X (Section 2.2);
+    X is n x K."""
+    A, dd = operator_parts(n, row_ptr, col, w, laplacian)
     X = np.asarray(X, dtype=np.float64)
-    return X - A @ X
+    if X.ndim == 1:
+        return dd * X - A @ X
+    return dd[:, None] * X - A @ X
+
+
+def dense_laplacian(n, row_ptr, col, w):
+    """Dense unnormalized L = D - W built entry by entry (tiny graphs)."""
+    W = np.zeros((n, n))
+    for i in range(n):
+        for p in range(row_ptr[i], row_ptr[i + 1]):
+            W[i, col[p]] = w[p]
+    return np.diag(W.sum(1)) - W
 
 
 def dense_normalized_laplacian(n, row_ptr, col, w):
@@ -106,31 +140,57 @@ def rhs(u, lam, y, eps, c, eta):
     return c * u - double_well_grad(u, eps) + eta * lam[:, None] * y
 
 
-def precond_diag(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=math.inf):
-    """Diagonal g of the feasible preconditioners for the normalized Laplacian
-    (Section 3.1): for infinite step size
+def precond_diag(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=math.inf, d=None):
+    """Diagonal g of the feasible preconditioners (Section 3.1).
+
+    Normalized Laplacian (d is None): for infinite step size
         G_Jd,s = 2(eps + eta Lambda + c),  G_Jp,s = 2 eps + eta Lambda + c + delta0,
         G_R,s  = eps lambda_max + eta Lambda + c + delta0;
     for a finite step size k the T_k versions
         G_Jd,ks = 2(1 + k(eps + c) + k eta Lambda),
         G_Jp,ks = (2 k eps + 1) + k(eta Lambda + c) + delta0,
-        G_R,ks  = 1 + k(eps lambda_max + eta Lambda + c) + delta0."""
+        G_R,ks  = 1 + k(eps lambda_max + eta Lambda + c) + delta0.
+    Unnormalized Laplacian (d the degrees): for infinite step size
+        G_Jd = 2(eps D + eta Lambda + c),  G_Jp = 2 eps D + eta Lambda + c + delta0,
+        G_R  = eps lambda_max + eta Lambda + c + delta0;
+    and for a finite step size k
+        G_Jd,k = 2(1 + k(eps D + eta Lambda + c)),
+        G_Jp,k = 1 + k(2 eps D + eta Lambda + c) + delta0,
+        G_R,k  = 1 + k(eps lambda_max + eta Lambda + c) + delta0."""
     el = eta * lam
+    if d is None:
+        if math.isinf(step_k):
+            if kind == "damped_jacobi":
+                return 2.0 * (eps + el + c)
+            if kind == "perturbed_jacobi":
+                return 2.0 * eps + el + c + delta0
+            if kind == "richardson":
+                return eps * lambda_max + el + c + delta0
+        else:
+            k = step_k
+            if kind == "damped_jacobi":
+                return 2.0 * (1.0 + k * (eps + c) + k * el)
+            if kind == "perturbed_jacobi":
+                return (2.0 * k * eps + 1.0) + k * (el + c) + delta0
+            if kind == "richardson":
+                return 1.0 + k * (eps * lambda_max + el + c) + delta0
+        raise ValueError(f"unknown preconditioner {kind}")
+    d = np.asarray(d, dtype=np.float64)
     if math.isinf(step_k):
         if kind == "damped_jacobi":
-            return 2.0 * (eps + el + c)
+            return 2.0 * (eps * d + el + c)
         if kind == "perturbed_jacobi":
-            return 2.0 * eps + el + c + delta0
+            return 2.0 * eps * d + el + c + delta0
         if kind == "richardson":
-            return eps * lambda_max + el + c + delta0
+            return eps * lambda_max + el + c + delta0 + 0.0 * d
     else:
         k = step_k
         if kind == "damped_jacobi":
-            return 2.0 * (1.0 + k * (eps + c) + k * el)
+            return 2.0 * (1.0 + k * (eps * d + el + c))
         if kind == "perturbed_jacobi":
-            return (2.0 * k * eps + 1.0) + k * (el + c) + delta0
+            return 1.0 + k * (2.0 * eps * d + el + c) + delta0
         if kind == "richardson":
-            return 1.0 + k * (eps * lambda_max + el + c) + delta0
+            return 1.0 + k * (eps * lambda_max + el + c) + delta0 + 0.0 * d
     raise ValueError(f"unknown preconditioner {kind}")
 
 
@@ -138,15 +198,15 @@ def precond_diag(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=mat
 # energy (Section 2.1)
 # ---------------------------------------------------------------------------
 
-def energy(n, row_ptr, col, w, U, labels, eps, eta):
-    """F(u) per column: (eps/2) u^T L_s u + (1/eps) sum W(u_i)
+def energy(n, row_ptr, col, w, U, labels, eps, eta, laplacian="normalized"):
+    """F(u) per column: (eps/2) u^T L_s u (or u^T L u) + (1/eps) sum W(u_i)
     + (eta/2) sum Lambda_i (u_i - y_i)^2 (Section 2.1)."""
     U = np.asarray(U, dtype=np.float64)
     if U.ndim == 1:
         U = U[:, None]
     K = U.shape[1]
     lam, y = fidelity(labels, K)
-    LU = laplacian_apply(n, row_ptr, col, w, U)
+    LU = laplacian_apply(n, row_ptr, col, w, U, laplacian)
     lap = 0.5 * eps * (U * LU).sum(0)
     well = ((U ** 2 - 1.0) ** 2).sum(0) / (4.0 * eps)
     fid = 0.5 * eta * (lam[:, None] * (U - y) ** 2).sum(0)
@@ -158,7 +218,8 @@ def energy(n, row_ptr, col, w, U, labels, eps, eta):
 # ---------------------------------------------------------------------------
 
 def dca_solve(n, row_ptr, col, w, labels, u0, *, eps, c, eta, precond, outer, sweeps,
-              delta0=1e-6, lambda_max=2.0, step_k=math.inf, record=True):
+              delta0=1e-6, lambda_max=2.0, step_k=math.inf, record=True,
+              laplacian="normalized"):
     """Run `outer` DCA steps of `sweeps` preconditioned sweeps each.
 
     Returns (U [n, K], energies [outer + 1, K], residual_sq [outer, sweeps, K])
@@ -170,19 +231,20 @@ def dca_solve(n, row_ptr, col, w, labels, u0, *, eps, c, eta, precond, outer, sw
     if U.ndim == 1:
         U = U[:, None]
     K = U.shape[1]
-    A = normalized_adjacency(n, row_ptr, col, w)
+    A, dd = operator_parts(n, row_ptr, col, w, laplacian)
     lam, y = fidelity(labels, K)
-    g = precond_diag(precond, lam, eps, c, eta, delta0, lambda_max, step_k)[:, None]
+    g = precond_diag(precond, lam, eps, c, eta, delta0, lambda_max, step_k,
+                     d=None if laplacian == "normalized" else dd)[:, None]
     energies = np.zeros((outer + 1, K))
     res = np.zeros((outer, sweeps, K))
 
     def T_apply(V):
-        # T = eps L_s + eta Lambda + c I (Section 3)
-        return eps * (V - A @ V) + eta * lam[:, None] * V + c * V
+        # T = eps L_s + eta Lambda + c I, or eps L + eta Lambda + c I (Section 3)
+        return eps * (dd[:, None] * V - A @ V) + eta * lam[:, None] * V + c * V
 
     for t in range(outer):
         if record:
-            energies[t] = energy(n, row_ptr, col, w, U, labels, eps, eta)
+            energies[t] = energy(n, row_ptr, col, w, U, labels, eps, eta, laplacian)
         b = rhs(U, lam, y, eps, c, eta)
         V = U.copy()
         for s in range(sweeps):
@@ -195,26 +257,27 @@ def dca_solve(n, row_ptr, col, w, labels, u0, *, eps, c, eta, precond, outer, sw
             V = V + r / g
         U = V
     if record:
-        energies[outer] = energy(n, row_ptr, col, w, U, labels, eps, eta)
+        energies[outer] = energy(n, row_ptr, col, w, U, labels, eps, eta, laplacian)
     return U, energies, res
 
 
-def power_max_eig(n, row_ptr, col, w, x0, iters=150):
-    """Power method for the largest eigenvalue of L_s (Section 3.1, used for
-    G_R,s; Section 5.1.1 runs 150 iterations).
+def power_max_eig(n, row_ptr, col, w, x0, iters=150, laplacian="normalized"):
+    """Power method for the largest eigenvalue of L_s or L (Section 3.1, used
+    for G_R,s and G_R; Section 5.1.1 runs 150 iterations).
 
-    x <- x0/||x0||; repeat iters times: x <- L_s x / ||L_s x||.  Returns
-    (rq, lambda_hat) with rq = x^T L_s x (x of unit norm) and
-    lambda_hat = min(2, 1.01 rq).
+    x <- x0/||x0||; repeat iters times: x <- L x / ||L x||.  Returns
+    (rq, lambda_hat) with rq = x^T L x (x of unit norm) and
+    lambda_hat = min(2 max_i dd_i, 1.01 rq) (dd = 1 for L_s, the degrees for L;
+    both caps are Prop. 3).
     """
-    A = normalized_adjacency(n, row_ptr, col, w)
+    A, dd = operator_parts(n, row_ptr, col, w, laplacian)
     x = np.asarray(x0, dtype=np.float64).reshape(-1)
     x = x / np.linalg.norm(x)
     for _ in range(iters):
-        y = x - A @ x
+        y = dd * x - A @ x
         x = y / np.linalg.norm(y)
-    rq = float(x @ (x - A @ x))
-    return rq, min(2.0, 1.01 * rq)
+    rq = float(x @ (dd * x - A @ x))
+    return rq, min(2.0 * float(dd.max()), 1.01 * rq)
 
 
 def assign_labels(U):

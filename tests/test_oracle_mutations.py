@@ -18,7 +18,8 @@ def _run_pins():
     """Run a set of pin checks against gl_oracle; return names that failed."""
     failed = []
     checks = {
-        "golden": lambda: pins.test_two_node_golden(go),
+        "golden": lambda: pins.test_two_node_golden(go, "two_node.json"),
+        "golden_unnormalized": lambda: pins.test_two_node_golden(go, "two_node_unnormalized.json"),
         "laplacian": lambda: pins.test_laplacian_properties(go, 1),
         "power": lambda: pins.test_power_method_closed_form(go, "C7", pins._cycle(7),
                                                             1 - math.cos(2 * math.pi * 3 / 7)),
@@ -43,7 +44,7 @@ def test_unmutated_oracle_passes_every_pin():
 
 _orig = {name: getattr(go, name) for name in
          ("rhs", "double_well_grad", "precond_diag", "normalized_weights", "fidelity",
-          "energy", "normalized_adjacency")}
+          "energy", "normalized_adjacency", "operator_parts")}
 
 
 def _m_grad_sign(u, eps):
@@ -58,12 +59,23 @@ def _m_rhs_wrong_c(u, lam, y, eps, c, eta):
     return u - go.double_well_grad(u, eps) + eta * lam[:, None] * y
 
 
-def _m_precond_half(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=math.inf):
-    return 0.5 * _orig["precond_diag"](kind, lam, eps, c, eta, delta0, lambda_max, step_k)
+def _m_precond_half(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=math.inf, d=None):
+    return 0.5 * _orig["precond_diag"](kind, lam, eps, c, eta, delta0, lambda_max, step_k, d)
 
 
-def _m_precond_no_eta(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=math.inf):
-    return _orig["precond_diag"](kind, 0 * lam, eps, c, eta, delta0, lambda_max, step_k)
+def _m_precond_no_eta(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=math.inf, d=None):
+    return _orig["precond_diag"](kind, 0 * lam, eps, c, eta, delta0, lambda_max, step_k, d)
+
+
+def _m_precond_no_degree(kind, lam, eps, c, eta, delta0=1e-6, lambda_max=2.0, step_k=math.inf,
+                         d=None):
+    # the unnormalized preconditioners with D replaced by I
+    return _orig["precond_diag"](kind, lam, eps, c, eta, delta0, lambda_max, step_k, None)
+
+
+def _m_parts_normalized(n, row_ptr, col, w, laplacian="normalized"):
+    # the unnormalized Laplacian silently replaced by L_s
+    return _orig["operator_parts"](n, row_ptr, col, w, "normalized")
 
 
 def _m_weights_row_only(n, row_ptr, col, w):
@@ -83,12 +95,12 @@ def _m_fidelity_flip(labels, K):
     return lam, -y
 
 
-def _m_energy_factor(n, row_ptr, col, w, U, labels, eps, eta):
+def _m_energy_factor(n, row_ptr, col, w, U, labels, eps, eta, laplacian="normalized"):
     U2 = np.asarray(U, dtype=np.float64)
     if U2.ndim == 1:
         U2 = U2[:, None]
     lam, y = go.fidelity(labels, U2.shape[1])
-    LU = go.laplacian_apply(n, row_ptr, col, w, U2)
+    LU = go.laplacian_apply(n, row_ptr, col, w, U2, laplacian)
     return eps * (U2 * LU).sum(0) + ((U2 ** 2 - 1) ** 2).sum(0) / (4 * eps) \
         + 0.5 * eta * (lam[:, None] * (U2 - y) ** 2).sum(0)
 
@@ -103,6 +115,8 @@ MUTANTS = {
     "degree index i for j": ("normalized_weights", _m_weights_wrong_index),
     "labels sign flipped": ("fidelity", _m_fidelity_flip),
     "energy Laplacian factor": ("energy", _m_energy_factor),
+    "unnormalized preconditioner without D": ("precond_diag", _m_precond_no_degree),
+    "unnormalized Laplacian replaced by L_s": ("operator_parts", _m_parts_normalized),
 }
 
 

@@ -12,7 +12,12 @@ Both oracle implementations (numpy and plain C) are held to:
   * energy decay F(u^{t+1}) <= F(u^t) and, for one sweep per step, the
     sharper Thm. 1 bound with M_0 = G - T;
   * invariants: sign symmetry, a fixed point, column decoupling, permutation
-    equivariance, split-run resume.
+    equivariance, split-run resume;
+  * for the unnormalized Laplacian L = D - W: a hand-derived two-node golden
+    (tests/golden/two_node_unnormalized.json), the explicit path Laplacian,
+    L 1 = 0, 2D >= L (Prop. 3), L = D^{1/2} L_s D^{1/2}, closed-form largest
+    eigenvalues, feasibility and the closed form of the sweeps with the
+    D-dependent preconditioners of Section 3.1, energy decay.
 """
 
 import json
@@ -61,8 +66,10 @@ def _fid(labels, K):
 # --------------------------------------------------------------------------
 
 @pytest.mark.parametrize("orc", ORACLES)
-def test_two_node_golden(orc):
-    gd = json.load(open(os.path.join(GOLDEN, "two_node.json")))
+@pytest.mark.parametrize("golden", ["two_node.json", "two_node_unnormalized.json"])
+def test_two_node_golden(orc, golden):
+    gd = json.load(open(os.path.join(GOLDEN, golden)))
+    lapl = gd.get("laplacian", "normalized")
     rp = np.array(gd["graph"]["row_ptr"], dtype=np.int64)
     col = np.array(gd["graph"]["col"], dtype=np.int32)
     w = np.array(gd["graph"]["weight"])
@@ -73,7 +80,7 @@ def test_two_node_golden(orc):
         U, en, rs = orc.dca_solve(2, rp, col, w, lab, u0, eps=gd["eps"], c=gd["c"], eta=gd["eta"],
                                   precond=case["precond"], outer=case["outer"],
                                   sweeps=case["sweeps"], delta0=case["delta0"],
-                                  lambda_max=case["lambda_max"], step_k=k)
+                                  lambda_max=case["lambda_max"], step_k=k, laplacian=lapl)
         want = np.array([float(Fraction(x)) for x in case["u"]])
         np.testing.assert_allclose(U[:, 0], want, rtol=0, atol=1e-15, err_msg=case["name"])
         if "residual_sq" in case:
@@ -405,3 +412,143 @@ def test_labels_rule():
     assert list(gl_oracle.assign_labels(U)) == [1, 0, 1]
     V = np.array([[0.2, 0.2, 0.1], [-1, 0.5, 0.5], [0, 0, 1]])
     assert list(gl_oracle.assign_labels(V)) == [0, 1, 2]
+
+
+# --------------------------------------------------------------------------
+# the unnormalized Laplacian L = D - W (Section 2.2) and its preconditioners
+# --------------------------------------------------------------------------
+
+def _dense_L(W):
+    return np.diag(W.sum(1)) - W
+
+
+def test_path3_unnormalized_laplacian_explicit():
+    # path 0-1-2 with unit weights: the combinatorial Laplacian, eigenvalues 0, 1, 3
+    g = dense_to_graph(np.array([[0, 1, 0], [1, 0, 1], [0, 1, 0]], dtype=float))
+    rp, col, w = g.numpy()
+    L = gl_oracle.dense_laplacian(3, rp, col, w)
+    np.testing.assert_allclose(L, [[1, -1, 0], [-1, 2, -1], [0, -1, 1]], atol=0)
+    np.testing.assert_allclose(np.linalg.eigvalsh(L), [0, 1, 3], atol=1e-14)
+    for orc in (gl_oracle, c_oracle):
+        got = orc.laplacian_apply(3, rp, col, w, np.eye(3), laplacian="unnormalized")
+        np.testing.assert_allclose(got, L, atol=0)
+
+
+@pytest.mark.parametrize("orc", ORACLES)
+@pytest.mark.parametrize("seed", range(6))
+def test_unnormalized_laplacian_properties(orc, seed):
+    rng = np.random.default_rng(100 + seed)
+    g = tiny_graph(int(rng.integers(3, 24)), 0.3, rng)
+    rp, col, w = g.numpy()
+    W = _dense_W(g)
+    d = W.sum(1)
+    # L 1 = 0 (Section 2.2)
+    z = orc.laplacian_apply(g.n, rp, col, w, np.ones((g.n, 1)), laplacian="unnormalized")
+    assert np.abs(z).max() < 1e-13 * d.max()
+    L = orc.laplacian_apply(g.n, rp, col, w, np.eye(g.n), laplacian="unnormalized")
+    np.testing.assert_allclose(L, L.T, atol=1e-15)
+    assert np.linalg.eigvalsh(L).min() > -1e-12 * d.max()
+    # Prop. 3: 2D - L = D + W is positive semidefinite
+    assert np.linalg.eigvalsh(2 * np.diag(d) - L).min() > -1e-12 * d.max()
+    # L = D^{1/2} L_s D^{1/2}
+    np.testing.assert_allclose(L, np.sqrt(d)[:, None] * _dense_Ls(W) * np.sqrt(d)[None, :],
+                               atol=1e-13 * d.max())
+    np.testing.assert_allclose(L, _dense_L(W), atol=1e-14 * d.max())
+    # L scales with the weights (L_s does not)
+    X = rng.standard_normal((g.n, 2))
+    a = orc.laplacian_apply(g.n, rp, col, w, X, laplacian="unnormalized")
+    b = orc.laplacian_apply(g.n, rp, col, 4.0 * w, X, laplacian="unnormalized")
+    np.testing.assert_allclose(b, 4.0 * a, atol=1e-13 * d.max())
+
+
+@pytest.mark.parametrize("orc", ORACLES)
+@pytest.mark.parametrize("name,g,lam", [
+    ("K5", _complete(5), 5.0),           # K_n: eigenvalue n (multiplicity n - 1)
+    ("K9", _complete(9), 9.0),
+    ("S6", _star(6), 6.0),               # star with m leaves: m + 1
+    ("C8", _cycle(8), 4.0),              # cycle: 2 - 2 cos(2 pi j / n)
+    ("C7", _cycle(7), 2 - 2 * math.cos(2 * math.pi * 3 / 7)),
+])
+def test_unnormalized_power_closed_form(orc, name, g, lam):
+    rp, col, w = g.numpy()
+    x0 = np.random.default_rng(11).uniform(-1, 1, g.n)
+    rq, lhat = orc.power_max_eig(g.n, rp, col, w, x0, iters=150, laplacian="unnormalized")
+    assert abs(rq - lam) < 1e-6 * lam, (name, rq, lam)
+    dmax = float(_dense_W(g).sum(1).max())
+    assert lhat == pytest.approx(min(2.0 * dmax, 1.01 * rq), rel=1e-15)
+    # the scaled graph scales the eigenvalue
+    rq3, _ = orc.power_max_eig(g.n, rp, col, 3.0 * w, x0, iters=150, laplacian="unnormalized")
+    assert abs(rq3 - 3 * lam) < 3e-6 * lam
+
+
+@pytest.mark.parametrize("kind", gl_oracle.PRECONDS)
+@pytest.mark.parametrize("step_k", [math.inf, 0.05, 1.0, 5.0])
+def test_unnormalized_preconditioner_feasible(kind, step_k):
+    for seed in range(4):
+        g, labels, _ = _setup(seed)
+        W = 2.5 * _dense_W(g)
+        d = W.sum(1)
+        L = _dense_L(W)
+        lam, _ = _fid(labels, 1)
+        eps, c, eta = 1.7, 2.3, 50.0
+        lmax = float(np.linalg.eigvalsh(L).max())
+        G = np.diag(gl_oracle.precond_diag(kind, lam, eps, c, eta, 1e-3, lmax, step_k, d=d))
+        T = eps * L + eta * np.diag(lam) + c * np.eye(g.n)
+        if not math.isinf(step_k):
+            T = np.eye(g.n) + step_k * T
+        assert np.linalg.eigvalsh(G - T).min() > 0
+
+
+@pytest.mark.parametrize("orc", ORACLES)
+@pytest.mark.parametrize("kind", gl_oracle.PRECONDS)
+@pytest.mark.parametrize("step_k", [math.inf, 0.5])
+def test_unnormalized_sweeps_closed_form(orc, kind, step_k):
+    for seed in range(3):
+        g, labels, u0 = _setup(seed, K=1)
+        rp, col, w = g.numpy()
+        w = 1.7 * w
+        W = 1.7 * _dense_W(g)
+        d = W.sum(1)
+        L = _dense_L(W)
+        lam, y = _fid(labels, 1)
+        eps, c, eta = 1.3, 3.0, 20.0
+        lmax = float(np.linalg.eigvalsh(L).max())
+        # G from its definition (Section 3.1), written here with D explicit
+        el = eta * lam
+        if math.isinf(step_k):
+            gd = {"damped_jacobi": 2 * (eps * d + el + c), "perturbed_jacobi": 2 * eps * d + el + c + 1e-2,
+                  "richardson": eps * lmax + el + c + 1e-2}[kind]
+        else:
+            k = step_k
+            gd = {"damped_jacobi": 2 * (1 + k * (eps * d + el + c)),
+                  "perturbed_jacobi": 1 + k * (2 * eps * d + el + c) + 1e-2,
+                  "richardson": 1 + k * (eps * lmax + el + c) + 1e-2}[kind]
+        want, _, _ = _closed_form_sweeps(L, lam, y, u0, eps, c, eta, gd, 3, step_k)
+        U, _, _ = orc.dca_solve(g.n, rp, col, w, labels, u0, eps=eps, c=c, eta=eta, precond=kind,
+                                outer=1, sweeps=3, delta0=1e-2, lambda_max=lmax, step_k=step_k,
+                                laplacian="unnormalized")
+        np.testing.assert_allclose(U, want, atol=1e-12)
+
+
+@pytest.mark.parametrize("orc", ORACLES)
+@pytest.mark.parametrize("kind", gl_oracle.PRECONDS)
+def test_unnormalized_energy_decreases(orc, kind):
+    for seed in range(4):
+        g, labels, u0 = _setup(seed, n=20, K=2)
+        rp, col, w = g.numpy()
+        eps, c, eta = 1.0, 3.0, 100.0
+        W = _dense_W(g)
+        lmax = float(np.linalg.eigvalsh(_dense_L(W)).max())
+        U, en, _ = orc.dca_solve(g.n, rp, col, w, labels, u0, eps=eps, c=c, eta=eta,
+                                 precond=kind, outer=25, sweeps=2, delta0=1e-6,
+                                 lambda_max=lmax, laplacian="unnormalized")
+        assert _convexity_ok(U, eps, c)
+        assert np.all(np.diff(en, axis=0) <= 1e-12 * np.abs(en[:-1]))
+        # the energy with L written as a double sum: u^T L u = 1/2 sum w_ij (u_i - u_j)^2
+        for k in range(2):
+            x = U[:, k]
+            lap = 0.5 * np.sum(W * (x[:, None] - x[None, :]) ** 2)
+            lam, y = _fid(labels, 2)
+            want = (eps / 2) * lap + np.sum((x ** 2 - 1) ** 2) / (4 * eps) \
+                + (eta / 2) * np.sum(lam * (x - y[:, k]) ** 2)
+            assert en[-1, k] == pytest.approx(want, rel=1e-12)
