@@ -61,7 +61,11 @@ typedef enum gl_dtype { GL_F64 = 0, GL_F32 = 1, GL_BF16 = 2, GL_F16 = 3 } gl_dty
  *   PERTURBED_JACOBI  G_Jp,s = 2 eps + c + eta Lambda + delta0
  *   RICHARDSON        G_R,s  = eps lambda_max + c + eta Lambda + delta0
  * and, for a finite step size k, the preconditioners of T_k = I + k T of the
- * same section (G_Jd,ks, G_Jp,ks, G_R,ks). */
+ * same section (G_Jd,ks, G_Jp,ks, G_R,ks).  With the unnormalized Laplacian
+ * (T = eps L + eta Lambda + c I) the same names select G_Jd = 2(eps D + eta
+ * Lambda + c), G_Jp = 2 eps D + eta Lambda + c + delta0, G_R = eps lambda_max
+ * + eta Lambda + c + delta0 and their step-size-k versions G_Jd,k, G_Jp,k,
+ * G_R,k (Section 3.1). */
 typedef enum gl_precond {
     GL_PC_DAMPED_JACOBI = 0,
     GL_PC_PERTURBED_JACOBI = 1,
@@ -80,6 +84,13 @@ typedef enum gl_precond {
  *           Fails with GL_E_INVALID_ARG when a halo exceeds the limit. */
 typedef enum gl_layout { GL_LAYOUT_AUTO = 0, GL_LAYOUT_DIRECT = 1, GL_LAYOUT_TILE = 2 } gl_layout;
 
+/* Graph Laplacian of the operator (Section 2.2):
+ *   NORMALIZED    L_s = I - D^{-1/2} W D^{-1/2} (the default);
+ *   UNNORMALIZED  L = D - W.  The operator stores w_ij rounded to its storage
+ *                 type and, as the diagonal, the row sums of those stored
+ *                 weights (so L 1 = 0 holds for the weights the sweeps use). */
+typedef enum gl_laplacian { GL_LAP_NORMALIZED = 0, GL_LAP_UNNORMALIZED = 1 } gl_laplacian;
+
 /* Weighted undirected graph in CSR form (Section 2.2), device memory.
  *   row_ptr  int64 [n+1], row_ptr[0] = 0, non-decreasing, row_ptr[n] = nnz
  *   col_idx  int32 [nnz], strictly increasing within a row, in [0, n),
@@ -97,6 +108,7 @@ typedef enum gl_layout { GL_LAYOUT_AUTO = 0, GL_LAYOUT_DIRECT = 1, GL_LAYOUT_TIL
  *            their node-ordered inputs and outputs in and out once per call
  *            (their workspaces grow accordingly).
  *   layout   gl_layout request.
+ *   laplacian gl_laplacian: L_s or L.
  * Every degree d_i = sum_j w_ij must be > 0. */
 typedef struct gl_graph {
     int64_t n;
@@ -107,14 +119,17 @@ typedef struct gl_graph {
     gl_dtype weight_dtype;
     const int32_t *order;
     int32_t layout;
+    int32_t laplacian;
 } gl_graph;
 
 /* Solver parameters (Section 3 and Section 3.1).
  *   eps > 0, c > 0, eta >= 0: the model's diffuse parameter, the convex-split
  *     constant and the fidelity weight;
  *   delta0 >= 0: the perturbation of G_Jp,s and G_R,s;
- *   lambda_max in (0, 2]: the estimate of the largest eigenvalue of L_s used
- *     by RICHARDSON (see gl_power_max_eig), ignored otherwise;
+ *   lambda_max > 0: the estimate of the largest eigenvalue of the operator's
+ *     Laplacian (L_s: at most 2; L: at most 2 max d_i, Prop. 3) used by
+ *     RICHARDSON (see gl_power_max_eig), ignored otherwise; it must not be
+ *     below the true largest eigenvalue for G_R to be feasible;
  *   step_k: INFINITY for the DCA without step size (Prop. 1), or a finite
  *     k > 0 for the step-size form T_k u = b_k, T_k = I + k T,
  *     b_k = u^t + k b^t (Lemma 1);
@@ -134,10 +149,11 @@ typedef struct gl_params {
 
 typedef struct gl_operator gl_operator;
 
-/* Build the normalized operator of `graph` (Section 2.2): validates the CSR
- * (see gl_graph), computes d_i = sum_j w_ij in F64 and stores
+/* Build the operator of `graph` (Section 2.2): validates the CSR (see
+ * gl_graph), computes d_i = sum_j w_ij in F64 and stores, for L_s,
  * what_ij = w_ij / sqrt(d_i d_j) rounded to `store_w` (GL_F64, GL_F32,
- * GL_BF16 or GL_F16) in library-owned device memory, with its own copy of the
+ * GL_BF16 or GL_F16), for L the rounded w_ij and the row sums of the stored
+ * weights as the diagonal, in library-owned device memory, with its own copy of the
  * index arrays; the caller may free `graph`'s arrays after return.  With an
  * order or a tile request the index layout is built on the host (the CSR
  * pattern is copied back once).  Synchronises `stream`.  Errors: GL_E_INVALID_ARG, GL_E_BAD_GRAPH (message
@@ -168,12 +184,14 @@ gl_status gl_laplacian_apply(const gl_operator *op, int32_t K, gl_dtype dtype,
 /* Device bytes of workspace that gl_power_max_eig needs (host out). */
 gl_status gl_power_workspace_size(const gl_operator *op, size_t *bytes);
 
-/* Power method for the largest eigenvalue of L_s (Section 3.1; Section 5.1.1
- * uses 150 iterations): x <- x0/|x0|, then `iters` times
- * x <- L_s x / |L_s x|, in F32 with F64 norms.  Host outputs:
- * *rayleigh = x^T L_s x of the final unit vector, *lambda_hat =
- * min(2, 1.01 * rayleigh), an upper estimate kept feasible by 2I >= L_s
- * (Prop. 3).  x0: device float [n], not all zero.  Synchronises `stream`. */
+/* Power method for the largest eigenvalue of the operator's Laplacian
+ * (Section 3.1; Section 5.1.1 uses 150 iterations): x <- x0/|x0|, then
+ * `iters` times x <- L x / |L x|, in F32 with F64 norms.  Host outputs:
+ * *rayleigh = x^T L x of the final unit vector (L_s or L, as the operator's),
+ * *lambda_hat = min(2 dmax, 1.01 * rayleigh) with dmax = 1 for L_s and the
+ * largest stored diagonal for L, an upper estimate kept feasible by
+ * 2I >= L_s and 2D >= L (Prop. 3).  x0: device float [n], not all zero.
+ * Synchronises `stream`. */
 gl_status gl_power_max_eig(const gl_operator *op, int32_t iters, const float *x0,
                            void *workspace, size_t workspace_bytes,
                            double *rayleigh, double *lambda_hat, void *stream);

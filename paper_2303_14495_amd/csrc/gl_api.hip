@@ -30,6 +30,9 @@ struct gl_operator {
     int64_t halo_total = 0, nblocks = 0;
     void* w = nullptr;
     double* degree = nullptr;
+    int32_t lap = GL_LAP_NORMALIZED;
+    void* dd = nullptr;   // unnormalized L: diagonal d (accumulator type, position order)
+    double dmax = 1.0;    // largest diagonal entry of the Laplacian (1 for L_s)
     int32_t G = 16, log2G = 4, tiles = 4, remap = 1;
     size_t bytes = 0;
 };
@@ -80,6 +83,7 @@ gl::RowLaunch row_launch(const gl_operator* op) {
     r.w = op->w;
     r.wdt = op->store_w;
     r.order = nullptr;  // an ordered operator is renumbered: kernels index positions
+    r.dd = op->dd;
     r.n = op->n;
     if (op->layout == gl::LAYOUT_TILE) {
         r.trp = (const int32_t*)op->rp;
@@ -149,6 +153,21 @@ hipError_t fill_double(double* p, int64_t n, double v, hipStream_t s) {
     return hipGetLastError();
 }
 
+// Coefficients of g_i = ga + gd dd_i + gl Lambda_i for every preconditioner of
+// Section 3.1 (dd_i = 1 for L_s, d_i for L): step size infinite / finite k.
+void precond_affine(int kind, const gl_params& p, double& ga, double& gd, double& gl_) {
+    if (std::isinf(p.step_k)) {
+        if (kind == GL_PC_DAMPED_JACOBI) { ga = 2.0 * p.c; gd = 2.0 * p.eps; gl_ = 2.0 * p.eta; }
+        else if (kind == GL_PC_PERTURBED_JACOBI) { ga = p.c + p.delta0; gd = 2.0 * p.eps; gl_ = p.eta; }
+        else { ga = p.eps * p.lambda_max + p.c + p.delta0; gd = 0.0; gl_ = p.eta; }
+        return;
+    }
+    const double k = p.step_k;
+    if (kind == GL_PC_DAMPED_JACOBI) { ga = 2.0 * (1.0 + k * p.c); gd = 2.0 * k * p.eps; gl_ = 2.0 * k * p.eta; }
+    else if (kind == GL_PC_PERTURBED_JACOBI) { ga = 1.0 + k * p.c + p.delta0; gd = 2.0 * k * p.eps; gl_ = k * p.eta; }
+    else { ga = 1.0 + k * (p.eps * p.lambda_max + p.c) + p.delta0; gd = 0.0; gl_ = k * p.eta; }
+}
+
 // g for unlabelled (lam = 0) and labelled (lam = 1) rows (Section 3.1).
 double precond_g(int kind, double lam, const gl_params& p) {
     const double el = p.eta * lam;
@@ -172,8 +191,8 @@ gl_status check_params(const gl_params* p) {
     if (!fin(p->delta0) || p->delta0 < 0) return fail(GL_E_INVALID_ARG, "delta0 must be finite and >= 0");
     if (p->precond < GL_PC_DAMPED_JACOBI || p->precond > GL_PC_RICHARDSON)
         return fail(GL_E_INVALID_ARG, "unknown preconditioner");
-    if (p->precond == GL_PC_RICHARDSON && (!fin(p->lambda_max) || p->lambda_max <= 0 || p->lambda_max > 2.0))
-        return fail(GL_E_INVALID_ARG, "lambda_max must lie in (0, 2] for the Richardson preconditioner");
+    if (p->precond == GL_PC_RICHARDSON && (!fin(p->lambda_max) || p->lambda_max <= 0))
+        return fail(GL_E_INVALID_ARG, "lambda_max must be finite and > 0 for the Richardson preconditioner");
     if (std::isnan(p->step_k) || p->step_k <= 0 || (std::isinf(p->step_k) && p->step_k < 0))
         return fail(GL_E_INVALID_ARG, "step_k must be > 0 or +INFINITY");
     if (p->outer_steps < 0) return fail(GL_E_INVALID_ARG, "outer_steps must be >= 0");
@@ -187,7 +206,7 @@ void launch_normalize(gl_operator* op, const gl_graph* g, hipStream_t s) {
     const unsigned grid = (unsigned)((op->n + 1 + 255) / 256);
     hipLaunchKernelGGL((gl::normalize_kernel<TIN, TOUT, OffT>), dim3(grid), dim3(256), 0, s, op->n, g->row_ptr,
                        g->col_idx, static_cast<const TIN*>(g->weight), op->degree, static_cast<OffT*>(op->rp),
-                       op->col, static_cast<TOUT*>(op->w));
+                       op->col, static_cast<TOUT*>(op->w), op->lap == GL_LAP_UNNORMALIZED ? 1 : 0);
 }
 
 template <typename TIN, typename TOUT>
@@ -216,6 +235,7 @@ void free_op(gl_operator* op) {
     (void)hipFree(op->hp);
     (void)hipFree(op->w);
     (void)hipFree(op->degree);
+    (void)hipFree(op->dd);
     delete op;
 }
 
@@ -224,7 +244,49 @@ void launch_fill(gl_operator* op, const gl_graph* g, const int32_t* src, const i
     const unsigned grid = (unsigned)((op->n + 255) / 256);
     hipLaunchKernelGGL((gl::fill_layout_kernel<TIN, TOUT>), dim3(grid), dim3(256), 0, s, op->n,
                        (const int32_t*)op->rp, src, op->order, pos_of, g->col_idx,
-                       static_cast<const TIN*>(g->weight), op->degree, static_cast<TOUT*>(op->w), op->col);
+                       static_cast<const TIN*>(g->weight), op->degree, static_cast<TOUT*>(op->w), op->col,
+                       op->lap == GL_LAP_UNNORMALIZED ? 1 : 0);
+}
+
+// Unnormalized operator: diagonal d of L = D - W as the row sums of the stored
+// weights (position order, accumulator type of the storage) and its maximum.
+template <typename TW, typename A>
+hipError_t launch_rowsum(gl_operator* op, hipStream_t s) {
+    const unsigned grid = (unsigned)((op->n + 255) / 256);
+    if (op->layout == gl::LAYOUT_DIRECT && op->idx64)
+        hipLaunchKernelGGL((gl::rowsum_kernel<TW, int64_t, A>), dim3(grid), dim3(256), 0, s, op->n,
+                           (const int64_t*)op->rp, (const TW*)op->w, (A*)op->dd);
+    else
+        hipLaunchKernelGGL((gl::rowsum_kernel<TW, int32_t, A>), dim3(grid), dim3(256), 0, s, op->n,
+                           (const int32_t*)op->rp, (const TW*)op->w, (A*)op->dd);
+    return hipGetLastError();
+}
+
+gl_status finish_unnormalized(gl_operator* op, hipStream_t s) {
+    if (op->lap != GL_LAP_UNNORMALIZED) return GL_OK;
+    const size_t es = op->store_w == GL_F64 ? 8 : 4;
+    if (hipMalloc(&op->dd, (size_t)op->n * es) != hipSuccess)
+        return fail(GL_E_NOMEM, "device allocation for the operator failed");
+    op->bytes += (size_t)op->n * es;
+    hipError_t e = hipSuccess;
+    switch (op->store_w) {
+        case GL_F64: e = launch_rowsum<double, double>(op, s); break;
+        case GL_F32: e = launch_rowsum<float, float>(op, s); break;
+        case GL_BF16: e = launch_rowsum<gl::bf16, float>(op, s); break;
+        default: e = launch_rowsum<gl::f16, float>(op, s); break;
+    }
+    std::vector<char> h((size_t)op->n * es);
+    if (e == hipSuccess) e = hipMemcpyAsync(h.data(), op->dd, h.size(), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess) return fail(GL_E_HIP, std::string("operator diagonal: ") + hipGetErrorString(e));
+    double m = 0.0;
+    for (int64_t i = 0; i < op->n; ++i) {
+        const double v = es == 8 ? ((const double*)h.data())[i] : (double)((const float*)h.data())[i];
+        if (!(v > 0.0) || !std::isfinite(v)) return fail(GL_E_BAD_GRAPH, "a stored row sums to a non-positive degree");
+        m = v > m ? v : m;
+    }
+    op->dmax = m;
+    return GL_OK;
 }
 
 template <typename TIN>
@@ -301,6 +363,8 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         return fail(GL_E_DTYPE, "input weights must be GL_F64 or GL_F32");
     if (dtype_size(store_w) == 0) return fail(GL_E_DTYPE, "unknown store_w");
     if (g->layout < GL_LAYOUT_AUTO || g->layout > GL_LAYOUT_TILE) return fail(GL_E_INVALID_ARG, "unknown layout");
+    if (g->laplacian != GL_LAP_NORMALIZED && g->laplacian != GL_LAP_UNNORMALIZED)
+        return fail(GL_E_INVALID_ARG, "unknown laplacian");
     const bool host_layout = g->order != nullptr || g->layout == GL_LAYOUT_TILE;
     if (host_layout && g->nnz > (int64_t)INT32_MAX)
         return fail(GL_E_INVALID_ARG, "an order or the tile layout needs nnz < 2^31");
@@ -311,6 +375,7 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     op->nnz = g->nnz;
     op->stored = g->nnz;
     op->store_w = store_w;
+    op->lap = g->laplacian;
     op->idx64 = g->nnz > (int64_t)INT32_MAX;
     if (hipGetDevice(&op->device) != hipSuccess) {
         delete op;
@@ -396,6 +461,11 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         else launch_normalize_out<float>(op, g, s);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             return cleanup_fail(GL_E_HIP, "weight normalization failed");
+        const gl_status su = finish_unnormalized(op, s);
+        if (su != GL_OK) {
+            const std::string m = gl_last_error();
+            return cleanup_fail(su, m);
+        }
         (void)hipFree(scratch);
         *out = op;
         return GL_OK;
@@ -466,6 +536,11 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     const bool fill_ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
     (void)hipFree(d_pos_of);
     if (!fill_ok) return cleanup_fail(GL_E_HIP, "weight normalization failed");
+    const gl_status su = finish_unnormalized(op, s);
+    if (su != GL_OK) {
+        const std::string m = gl_last_error();
+        return cleanup_fail(su, m);
+    }
     (void)hipFree(d_src);
     (void)hipFree(scratch);
     *out = op;
@@ -501,7 +576,8 @@ gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* st
     if (stream_bytes) {
         const int64_t rp = (op->n + 1) * (op->idx64 ? 8 : 4);
         const int64_t idx = tile ? op->stored * 2 + op->halo_total * 4 + (op->nblocks + 1) * 4 : op->stored * 4;
-        *stream_bytes = rp + idx + op->stored * (int64_t)dtype_size(op->store_w);
+        *stream_bytes = rp + idx + op->stored * (int64_t)dtype_size(op->store_w) +
+                        (op->dd ? op->n * (op->store_w == GL_F64 ? 8 : 4) : 0);
     }
     return GL_OK;
 }
@@ -572,6 +648,7 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
             a.op.hp = op->hp;
             a.op.order = nullptr;
             a.op.n = op->n;
+            a.dd = (const float*)op->dd;
             a.x = x;
             a.y = y;
             a.scale = sc;
@@ -597,10 +674,10 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
         switch (op->store_w) {
 #define GL_POW(T)                                                                                   \
     if (op->idx64) {                                                                                \
-        gl::PowerArgs<T, int64_t> a{(const int64_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, nullptr, geo, mode}; \
+        gl::PowerArgs<T, int64_t> a{(const int64_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, nullptr, (const float*)op->dd, geo, mode}; \
         hipLaunchKernelGGL((gl::power_kernel<T, int64_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
     } else {                                                                                        \
-        gl::PowerArgs<T, int32_t> a{(const int32_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, nullptr, geo, mode}; \
+        gl::PowerArgs<T, int32_t> a{(const int32_t*)op->rp, op->col, (const T*)op->w, x, y, sc, partials, nullptr, (const float*)op->dd, geo, mode}; \
         hipLaunchKernelGGL((gl::power_kernel<T, int32_t>), dim3((unsigned)r.grid), dim3(256), 0, s, a); \
     }
             case GL_F32: GL_POW(float) break;
@@ -640,7 +717,7 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
     if (!(h[1] > 0) || !std::isfinite(h[0]) || !std::isfinite(h[1]))
         return fail(GL_E_NONFINITE, "power method: x0 is zero or the iteration is not finite");
     *rayleigh = h[0] / h[1];
-    *lambda_hat = std::fmin(2.0, 1.01 * *rayleigh);
+    *lambda_hat = std::fmin(2.0 * op->dmax, 1.01 * *rayleigh);  // 2D >= L, 2I >= L_s (Prop. 3)
     return GL_OK;
 }
 
@@ -696,8 +773,10 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
     L.partials = stats ? partials : nullptr;
     const double g0 = precond_g(p.precond, 0.0, p), g1 = precond_g(p.precond, 1.0, p);
     const bool inf_k = std::isinf(p.step_k);
-    const double coef[11] = {p.eps, p.c, p.eta, 1.0 / p.eps, 0.5 * p.eps, 0.25 / p.eps, 0.5 * p.eta,
-                             1.0 / g0, 1.0 / g1, inf_k ? 0.0 : 1.0, inf_k ? 1.0 : p.step_k};
+    double ga = 0, gd = 0, gll = 0;
+    precond_affine(p.precond, p, ga, gd, gll);
+    const double coef[14] = {p.eps, p.c, p.eta, 1.0 / p.eps, 0.5 * p.eps, 0.25 / p.eps, 0.5 * p.eta,
+                             1.0 / g0, 1.0 / g1, inf_k ? 0.0 : 1.0, inf_k ? 1.0 : p.step_k, ga, gd, gll};
     std::memcpy(L.coef, coef, sizeof(coef));
 
     const int64_t slen = gl_stats_length(K, T, m);
@@ -787,8 +866,10 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     }
     const double g0 = precond_g(p.precond, 0.0, p), g1 = precond_g(p.precond, 1.0, p);
     const bool inf_k = std::isinf(p.step_k);
-    const double coef[11] = {p.eps, p.c, p.eta, 1.0 / p.eps, 0.5 * p.eps, 0.25 / p.eps, 0.5 * p.eta,
-                             1.0 / g0, 1.0 / g1, inf_k ? 0.0 : 1.0, inf_k ? 1.0 : p.step_k};
+    double ga = 0, gd = 0, gll = 0;
+    precond_affine(p.precond, p, ga, gd, gll);
+    const double coef[14] = {p.eps, p.c, p.eta, 1.0 / p.eps, 0.5 * p.eps, 0.25 / p.eps, 0.5 * p.eta,
+                             1.0 / g0, 1.0 / g1, inf_k ? 0.0 : 1.0, inf_k ? 1.0 : p.step_k, ga, gd, gll};
     std::memcpy(L.coef, coef, sizeof(coef));
     L.ut = ut;
     // seed P with u^t so every timed sweep gathers finite values

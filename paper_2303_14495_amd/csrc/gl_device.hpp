@@ -120,6 +120,11 @@ __device__ __forceinline__ void load_row(const T* __restrict__ p, A (&out)[K]) {
     for (int k = 0; k < K; ++k) out[k] = cvt<A>(vals[k]);
 }
 
+// Fused multiply-add with one rounding, written out where the result must not
+// depend on how the compiler contracts an expression in a given kernel.
+__device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
+__device__ __forceinline__ double fma_acc(double a, double b, double c) { return __builtin_fma(a, b, c); }
+
 // runtime-index read of a register array without spilling it to scratch
 template <int K, typename A>
 __device__ __forceinline__ A pick(const A (&z)[K], int k) {

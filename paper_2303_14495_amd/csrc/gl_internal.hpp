@@ -19,6 +19,7 @@ struct RowLaunch {
     const void* w;        // normalized weights in the operator's storage type
     gl_dtype wdt;
     const int32_t* order; // node of each position, or nullptr
+    const void* dd;       // diagonal of L = D - W in the accumulator type, or nullptr (L_s)
     int64_t n;
     int64_t grid;
     // direct layout
@@ -43,8 +44,8 @@ struct SweepLaunch {
     const int32_t* labels;
     void* partials;
     int32_t energy;
-    // eps, c, eta, 1/eps, eps/2, 1/(4 eps), eta/2, 1/g0, 1/g1, alpha, kappa
-    double coef[11];
+    // eps, c, eta, 1/eps, eps/2, 1/(4 eps), eta/2, 1/g0, 1/g1, alpha, kappa, ga, gd, gl
+    double coef[14];
 };
 
 // Thread-local message returned by gl_last_error().

@@ -23,8 +23,9 @@ template <typename A> struct SweepCoef {
     A eps, c, eta;          // model parameters
     A inv_eps;              // 1 / eps
     A half_eps, quarter_inv_eps, half_eta;  // energy prefactors
-    A ginv0, ginv1;         // 1 / g for unlabelled (Lambda = 0) and labelled rows
+    A ginv0, ginv1;         // 1 / g for unlabelled (Lambda = 0) and labelled rows (L_s)
     A alpha, kappa;         // r = alpha (u^t - v) + kappa (b - T v)
+    A ga, gd, gl;           // unnormalized L: g_i = ga + gd d_i + gl Lambda_i
 };
 
 template <typename TW, typename TU, typename OffT> struct SweepArgs {
@@ -37,6 +38,7 @@ template <typename TW, typename TU, typename OffT> struct SweepArgs {
     TU* vout;          // v^{s+1}; nullptr for the energy-only pass
     const int32_t* labels;
     const int32_t* order;  // node of each row position, or nullptr (identity)
+    const A* dd;       // diagonal d_i of L = D - W, or nullptr for L_s (diagonal 1)
     A* partials;       // [2K][grid] block partial sums, or nullptr
     RowGeom g;
     int32_t energy;    // also accumulate the energy terms (vin == ut)
@@ -65,7 +67,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, in
             const int64_t node = a.order ? (int64_t)a.order[row] : row;
             const int32_t lab = a.labels[node];
             const A lam = lab >= 0 ? (A)1 : (A)0;
-            const A ginv = lab >= 0 ? a.k.ginv1 : a.k.ginv0;
+            const A dl = a.dd ? a.dd[node] : (A)1;
+            const A ginv = a.dd ? (A)1 / (a.k.ga + a.k.gd * dl + a.k.gl * lam)
+                                : (lab >= 0 ? a.k.ginv1 : a.k.ginv0);
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int k = q + c * G;
@@ -77,13 +81,15 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, in
                     const A y = lab < 0 ? (A)0
                               : (K == 1 ? (lab == 1 ? (A)1 : (A)-1) : (lab == k ? (A)1 : (A)-1));
                     const A rhs = a.k.c * u - (u * u * u - u) * a.k.inv_eps + a.k.eta * lam * y;
-                    const A tv = a.k.eps * (v - zk) + (a.k.eta * lam + a.k.c) * v;
+                    const A lv = a.dd ? dl * v - zk : v - zk;  // (L v)_i or (L_s v)_i
+                    const A tv = a.k.eps * lv + (a.k.eta * lam + a.k.c) * v;
                     const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
                     if (a.vout) a.vout[at] = store_as<TU>::from(v + r * ginv);
                     r_acc[c] += r * r;
                     if (a.energy) {
                         const A u2m1 = u * u - (A)1, dy = u - y;
-                        e_acc[c] += a.k.half_eps * (u * u - u * zk) + a.k.quarter_inv_eps * u2m1 * u2m1 +
+                        const A ulu = fma_acc(u, a.dd ? dl * u : u, -(u * zk));  // u (L u)_i, one rounding
+                        e_acc[c] += a.k.half_eps * ulu + a.k.quarter_inv_eps * u2m1 * u2m1 +
                                     a.k.half_eta * lam * dy * dy;
                     }
                 }
@@ -100,7 +106,7 @@ __global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a
     sweep_block<K>(a, b, (int64_t)gridDim.x);
 }
 
-// Y = X - What X  (L_s X, Section 2.2)
+// Y = X - What X (L_s X) or Y = D X - W X (L X), Section 2.2
 template <typename TW, typename TU, typename OffT> struct LapArgs {
     const OffT* rp;
     const int32_t* col;
@@ -108,6 +114,7 @@ template <typename TW, typename TU, typename OffT> struct LapArgs {
     const TU* x;
     TU* y;
     const int32_t* order;
+    const typename acc_of<TU>::type* dd;  // d_i of L, or nullptr for L_s
     RowGeom g;
 };
 
@@ -132,15 +139,17 @@ __global__ __launch_bounds__(kBlock) void laplacian_kernel(LapArgs<TW, TU, OffT>
                 const int k = q + c * G;
                 if (k < K) {
                     const int64_t at = node * K + k;
-                    a.y[at] = store_as<TU>::from(cvt<A>(a.x[at]) - pick<K>(z, k));
+                    const A xv = cvt<A>(a.x[at]);
+                    a.y[at] = store_as<TU>::from((a.dd ? a.dd[node] * xv : xv) - pick<K>(z, k));
                 }
             }
         }
     }
 }
 
-// Power-method pass on float vectors.  mode 0: y = s (x - What x) with s = *scale,
-// partial[0] = sum y^2.  mode 1: partial[0] = sum x (x - What x), partial[1] = sum x^2.
+// Power-method pass on float vectors with lx = L_s x = x - What x (or L x =
+// d x - W x).  mode 0: y = s lx with s = *scale, partial[0] = sum y^2.
+// mode 1: partial[0] = sum x lx, partial[1] = sum x^2.
 template <typename TW, typename OffT> struct PowerArgs {
     const OffT* rp;
     const int32_t* col;
@@ -150,6 +159,7 @@ template <typename TW, typename OffT> struct PowerArgs {
     const float* scale;
     float* partials;  // [2][grid]
     const int32_t* order;
+    const float* dd;  // d_i of L, or nullptr for L_s
     RowGeom g;
     int32_t mode;
 };
@@ -171,7 +181,7 @@ __global__ __launch_bounds__(kBlock) void power_kernel(PowerArgs<TW, OffT> a) {
         if (row < a.g.n && q == 0) {
             const int64_t node = a.order ? (int64_t)a.order[row] : row;
             const float xv = a.x[node];
-            const float lx = xv - z[0];
+            const float lx = (a.dd ? a.dd[node] * xv : xv) - z[0];
             if (a.mode == 0) {
                 const float yv = s * lx;
                 a.y[node] = yv;
@@ -354,11 +364,12 @@ __global__ void degree_kernel(int64_t n, const int64_t* __restrict__ rp, const T
 
 // what_ij = w_ij / sqrt(d_i d_j) in double, rounded once to TOUT; the index
 // arrays are copied (row offsets narrowed to OffT) in the same pass.
+// raw != 0 (unnormalized L = D - W): w_ij itself, rounded once to TOUT.
 template <typename TIN, typename TOUT, typename OffT>
 __global__ void normalize_kernel(int64_t n, const int64_t* __restrict__ rp, const int32_t* __restrict__ col,
                                  const TIN* __restrict__ w, const double* __restrict__ d,
                                  OffT* __restrict__ rp_out, int32_t* __restrict__ col_out,
-                                 TOUT* __restrict__ w_out) {
+                                 TOUT* __restrict__ w_out, int32_t raw) {
     const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (i > n) return;
     rp_out[i] = (OffT)rp[i];
@@ -367,8 +378,21 @@ __global__ void normalize_kernel(int64_t n, const int64_t* __restrict__ rp, cons
     for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
         const int32_t j = col[p];
         col_out[p] = j;
-        w_out[p] = store_as<TOUT>::from((double)w[p] / sqrt(di * d[j]));
+        w_out[p] = store_as<TOUT>::from(raw ? (double)w[p] : (double)w[p] / sqrt(di * d[j]));
     }
+}
+
+// Diagonal of the unnormalized operator as stored: dd_p = sum of the row's
+// stored (rounded) weights, summed in double in storage order, rounded to A.
+// Keeps L 1 = 0 for the weights the sweeps actually use.
+template <typename TW, typename OffT, typename A>
+__global__ void rowsum_kernel(int64_t n, const OffT* __restrict__ rp, const TW* __restrict__ w,
+                              A* __restrict__ dd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t p = rp[i]; p < rp[i + 1]; ++p) s += cvt<double>(w[p]);
+    dd[i] = (A)s;
 }
 
 }  // namespace gl

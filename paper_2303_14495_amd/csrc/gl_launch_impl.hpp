@@ -21,6 +21,7 @@ static SweepArgs<TW, TU, OffT> make_sweep_args(const SweepLaunch& L) {
     a.vout = static_cast<TU*>(L.vout);
     a.labels = L.labels;
     a.order = L.r.order;
+    a.dd = static_cast<const A*>(L.r.dd);
     a.partials = static_cast<A*>(L.partials);
     a.g = RowGeom{L.r.n, L.r.rows_per_block, L.r.G, L.r.log2G, L.r.tiles, L.r.remap};
     a.energy = L.energy;
@@ -35,6 +36,9 @@ static SweepArgs<TW, TU, OffT> make_sweep_args(const SweepLaunch& L) {
     a.k.ginv1 = (A)L.coef[8];
     a.k.alpha = (A)L.coef[9];
     a.k.kappa = (A)L.coef[10];
+    a.k.ga = (A)L.coef[11];
+    a.k.gd = (A)L.coef[12];
+    a.k.gl = (A)L.coef[13];
     return a;
 }
 
@@ -61,6 +65,7 @@ static hipError_t tile_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
     a.vin = static_cast<const TU*>(L.vin);
     a.vout = static_cast<TU*>(L.vout);
     a.labels = L.labels;
+    a.dd = static_cast<const A*>(L.r.dd);
     a.partials = static_cast<A*>(L.partials);
     a.energy = L.energy;
     const SweepArgs<TW, TU, int32_t> d = make_sweep_args<TW, TU, int32_t>(L);
@@ -87,6 +92,7 @@ static hipError_t tile_laplacian_k(int K, const RowLaunch& r, const void* x, voi
     a.op = tile_op(r);
     a.x = static_cast<const TU*>(x);
     a.y = static_cast<TU*>(y);
+    a.dd = static_cast<const A*>(r.dd);
     const dim3 grid((unsigned)r.grid), block(kBlock);
     const size_t lds = (size_t)r.hmax * K * sizeof(A);
     switch (K) {
@@ -130,6 +136,7 @@ static hipError_t laplacian_k(int K, const RowLaunch& r, const void* x, void* y,
     a.x = static_cast<const TU*>(x);
     a.y = static_cast<TU*>(y);
     a.order = r.order;
+    a.dd = static_cast<const typename acc_of<TU>::type*>(r.dd);
     a.g = RowGeom{r.n, r.rows_per_block, r.G, r.log2G, r.tiles, r.remap};
     const dim3 grid((unsigned)r.grid), block(kBlock);
     switch (K) {

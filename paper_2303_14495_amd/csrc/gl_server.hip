@@ -68,6 +68,7 @@ __device__ __forceinline__ SweepArgs<TW, TU, int32_t> served_args(const ServedDe
     a.vout = static_cast<TU*>(d.vout);
     a.labels = d.labels;
     a.order = nullptr;
+    a.dd = nullptr;  // served solves use L_s
     a.partials = static_cast<float*>(d.partials);
     a.g = RowGeom{d.n, d.rows_per_block, d.G, d.log2G, d.tiles, 0};
     a.energy = d.energy;
@@ -82,6 +83,7 @@ __device__ __forceinline__ SweepArgs<TW, TU, int32_t> served_args(const ServedDe
     a.k.ginv1 = d.coef[8];
     a.k.alpha = d.coef[9];
     a.k.kappa = d.coef[10];
+    a.k.ga = a.k.gd = a.k.gl = 0.f;
     return a;
 }
 
@@ -433,15 +435,15 @@ struct gl_server {
         switch (cfg.store_w) {
             case GL_F32:
                 hipLaunchKernelGGL((gl::normalize_kernel<double, float, int32_t>), dim3(grid1), dim3(256), 0, st, s.n,
-                                   s.d_rp64, s.d_colin, s.d_win, s.d_deg, s.d_rp, s.d_col, (float*)s.d_w);
+                                   s.d_rp64, s.d_colin, s.d_win, s.d_deg, s.d_rp, s.d_col, (float*)s.d_w, 0);
                 break;
             case GL_BF16:
                 hipLaunchKernelGGL((gl::normalize_kernel<double, gl::bf16, int32_t>), dim3(grid1), dim3(256), 0, st,
-                                   s.n, s.d_rp64, s.d_colin, s.d_win, s.d_deg, s.d_rp, s.d_col, (gl::bf16*)s.d_w);
+                                   s.n, s.d_rp64, s.d_colin, s.d_win, s.d_deg, s.d_rp, s.d_col, (gl::bf16*)s.d_w, 0);
                 break;
             default:
                 hipLaunchKernelGGL((gl::normalize_kernel<double, gl::f16, int32_t>), dim3(grid1), dim3(256), 0, st,
-                                   s.n, s.d_rp64, s.d_colin, s.d_win, s.d_deg, s.d_rp, s.d_col, (gl::f16*)s.d_w);
+                                   s.n, s.d_rp64, s.d_colin, s.d_win, s.d_deg, s.d_rp, s.d_col, (gl::f16*)s.d_w, 0);
                 break;
         }
         const int64_t cells = s.n * s.K;

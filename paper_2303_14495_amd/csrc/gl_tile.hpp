@@ -237,6 +237,7 @@ template <typename TU, typename A> struct TileSweepArgs {
     const TU* vin;
     TU* vout;  // nullptr: energy-only pass
     const int32_t* labels;
+    const A* dd;  // d_i of L = D - W by position, or nullptr for L_s
     A* partials;
     int32_t energy;
     SweepCoef<A> k;
@@ -253,6 +254,7 @@ __global__ __launch_bounds__(256) void tile_sweep_kernel(TileSweepArgs<TU, typen
     TileRows rows;
     int32_t lab[kTilePasses];
     A uu[kTilePasses][CPL], vv[kTilePasses][CPL];
+    A dls[kTilePasses];
     A e_acc[CPL], r_acc[CPL];
 #pragma unroll
     for (int c = 0; c < CPL; ++c) e_acc[c] = r_acc[c] = (A)0;
@@ -260,6 +262,7 @@ __global__ __launch_bounds__(256) void tile_sweep_kernel(TileSweepArgs<TU, typen
 #pragma unroll
         for (int tt = 0; tt < kTilePasses; ++tt) {
             lab[tt] = r.ok[tt] ? a.labels[r.node[tt]] : -1;
+            dls[tt] = (a.dd && r.ok[tt]) ? a.dd[r.node[tt]] : (A)1;
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int k = q + c * kTileG;
@@ -275,7 +278,8 @@ __global__ __launch_bounds__(256) void tile_sweep_kernel(TileSweepArgs<TU, typen
         if (!rows.ok[tt]) return;
         const int32_t l = lab[tt];
         const A lam = l >= 0 ? (A)1 : (A)0;
-        const A ginv = l >= 0 ? a.k.ginv1 : a.k.ginv0;
+        const A dl = dls[tt];
+        const A ginv = a.dd ? (A)1 / (a.k.ga + a.k.gd * dl + a.k.gl * lam) : (l >= 0 ? a.k.ginv1 : a.k.ginv0);
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
             const int k = q + c * kTileG;
@@ -284,13 +288,15 @@ __global__ __launch_bounds__(256) void tile_sweep_kernel(TileSweepArgs<TU, typen
                 const A u = uu[tt][c], v = vv[tt][c];
                 const A y = l < 0 ? (A)0 : (K == 1 ? (l == 1 ? (A)1 : (A)-1) : (l == k ? (A)1 : (A)-1));
                 const A rhs = a.k.c * u - (u * u * u - u) * a.k.inv_eps + a.k.eta * lam * y;
-                const A tv = a.k.eps * (v - zk) + (a.k.eta * lam + a.k.c) * v;
+                const A lv = a.dd ? dl * v - zk : v - zk;
+                const A tv = a.k.eps * lv + (a.k.eta * lam + a.k.c) * v;
                 const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
                 if (a.vout) a.vout[rows.node[tt] * K + k] = store_as<TU>::from(v + r * ginv);
                 r_acc[c] += r * r;
                 if (a.energy) {
                     const A u2m1 = u * u - (A)1, dy = u - y;
-                    e_acc[c] += a.k.half_eps * (u * u - u * zk) + a.k.quarter_inv_eps * u2m1 * u2m1 +
+                    const A ulu = fma_acc(u, a.dd ? dl * u : u, -(u * zk));  // u (L u)_i, one rounding
+                    e_acc[c] += a.k.half_eps * ulu + a.k.quarter_inv_eps * u2m1 * u2m1 +
                                 a.k.half_eta * lam * dy * dy;
                 }
             }
@@ -300,11 +306,12 @@ __global__ __launch_bounds__(256) void tile_sweep_kernel(TileSweepArgs<TU, typen
     if (a.partials) block_stats<K, CPL>(e_acc, r_acc, kTileG, a.partials, (int64_t)gridDim.x, b);
 }
 
-// Y = X - What X on the tile layout
+// Y = X - What X (or D X - W X) on the tile layout
 template <typename TU> struct TileLapArgs {
     TileOp op;
     const TU* x;
     TU* y;
+    const typename acc_of<TU>::type* dd;  // d_i of L by position, or nullptr for L_s
 };
 
 template <int K, typename TW, typename TU>
@@ -322,7 +329,10 @@ __global__ __launch_bounds__(256) void tile_laplacian_kernel(TileLapArgs<TU> a) 
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int k = q + c * kTileG;
-                if (r.ok[tt] && k < K) xx[tt][c] = cvt<A>(a.x[r.node[tt] * K + k]);
+                if (r.ok[tt] && k < K) {
+                    const A xv = cvt<A>(a.x[r.node[tt] * K + k]);
+                    xx[tt][c] = a.dd ? a.dd[r.node[tt]] * xv : xv;
+                }
             }
     };
     auto finish = [&](auto TT, const A (&zs)[CPL]) {
@@ -344,6 +354,7 @@ struct TilePowerArgs {
     float* y;
     const float* scale;
     float* partials;
+    const float* dd;  // d_i of L by position, or nullptr for L_s
     int32_t mode;
 };
 
@@ -353,17 +364,20 @@ __global__ __launch_bounds__(256) void tile_power_kernel(TilePowerArgs a) {
     float* hv = reinterpret_cast<float*>(smem_raw);
     const int q = threadIdx.x & (kTileG - 1);
     TileRows rows;
-    float xx[kTilePasses];
+    float xx[kTilePasses], dx[kTilePasses];
     const float s = a.mode == 0 ? *a.scale : 1.0f;
     float p0 = 0.f, p1 = 0.f;
     auto prefetch = [&](TileRows& r) {
 #pragma unroll
-        for (int tt = 0; tt < kTilePasses; ++tt) xx[tt] = (r.ok[tt] && q == 0) ? a.x[r.node[tt]] : 0.f;
+        for (int tt = 0; tt < kTilePasses; ++tt) {
+            xx[tt] = (r.ok[tt] && q == 0) ? a.x[r.node[tt]] : 0.f;
+            dx[tt] = (a.dd && r.ok[tt] && q == 0) ? a.dd[r.node[tt]] * xx[tt] : xx[tt];
+        }
     };
     auto finish = [&](auto TT, const float (&z)[1]) {
         constexpr int tt = decltype(TT)::value;
         if (!rows.ok[tt] || q != 0) return;
-        const float lx = xx[tt] - z[0];
+        const float lx = dx[tt] - z[0];
         if (a.mode == 0) {
             const float yv = s * lx;
             a.y[rows.node[tt]] = yv;
@@ -382,12 +396,13 @@ __global__ __launch_bounds__(256) void tile_power_kernel(TilePowerArgs a) {
 // normalized weight of source entry src[e] (w / sqrt(d_i d_j), i the node of p),
 // or 0 when src[e] < 0 (padding).  col_out (direct layout only) receives the
 // source column, mapped through pos_of (node -> position) when ordered.
+// raw != 0 (unnormalized L = D - W): the weight itself, rounded once.
 template <typename TIN, typename TOUT>
 __global__ void fill_layout_kernel(int64_t n, const int32_t* __restrict__ rp_out, const int32_t* __restrict__ src,
                                    const int32_t* __restrict__ order, const int32_t* __restrict__ pos_of,
                                    const int32_t* __restrict__ col, const TIN* __restrict__ w,
                                    const double* __restrict__ d, TOUT* __restrict__ w_out,
-                                   int32_t* __restrict__ col_out) {
+                                   int32_t* __restrict__ col_out, int32_t raw) {
     const int64_t p = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
     if (p >= n) return;
     const int64_t i = order ? (int64_t)order[p] : p;
@@ -396,7 +411,7 @@ __global__ void fill_layout_kernel(int64_t n, const int32_t* __restrict__ rp_out
         const int32_t s = src[e];
         if (s >= 0) {
             const int32_t j = col[s];
-            w_out[e] = store_as<TOUT>::from((double)w[s] / sqrt(di * d[j]));
+            w_out[e] = store_as<TOUT>::from(raw ? (double)w[s] : (double)w[s] / sqrt(di * d[j]));
             if (col_out) col_out[e] = pos_of ? pos_of[j] : j;
         } else {
             w_out[e] = store_as<TOUT>::from(0.0);

@@ -38,10 +38,11 @@ class _Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p),
                 ("weight_dtype", ctypes.c_int32), ("order", ctypes.c_void_p),
-                ("layout", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("laplacian", ctypes.c_int32)]
 
 
 LAYOUTS = {"auto": 0, "direct": 1, "tile": 2}
+LAPLACIANS = {"normalized": 0, "unnormalized": 1}
 
 
 class _Params(ctypes.Structure):
@@ -151,14 +152,15 @@ def split_stats(stats: torch.Tensor, K: int, outer: int, sweeps: int):
 
 
 class Operator:
-    """Normalized graph operator What = D^{-1/2} W D^{-1/2} held on the GPU.
+    """Graph operator held on the GPU: the normalized What = D^{-1/2} W D^{-1/2}
+    of L_s (laplacian="normalized") or W and D of L = D - W ("unnormalized").
 
     row_ptr (int64 [n+1]), col (int32 [nnz]) and weight (float64 or float32
     [nnz]) are CUDA tensors of a symmetric graph without self-loops.
     """
 
     def __init__(self, row_ptr, col, weight, store_w: str = "f32", stream=None, order=None,
-                 layout: str = "auto"):
+                 layout: str = "auto", laplacian: str = "normalized"):
         lib = load_library()
         if not (row_ptr.is_cuda and col.is_cuda and weight.is_cuda):
             raise ValueError("graph tensors must live on the GPU")
@@ -177,7 +179,9 @@ class Operator:
             order_t = order.to(device=row_ptr.device, dtype=torch.int32).contiguous()
         g = _Graph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
                    self.weight.data_ptr(), DTYPES[DTYPE_OF_TORCH[weight.dtype]],
-                   order_t.data_ptr() if order_t is not None else None, LAYOUTS[layout])
+                   order_t.data_ptr() if order_t is not None else None, LAYOUTS[layout],
+                   LAPLACIANS[laplacian])
+        self.laplacian = laplacian
         handle = ctypes.c_void_p()
         self._h = None
         _check(lib.gl_operator_create(ctypes.byref(g), DTYPES[store_w], _stream_handle(stream),
@@ -216,7 +220,8 @@ class Operator:
         return {"n": n.value, "nnz": nnz.value, "lanes_per_row": lanes.value,
                 "device_bytes": by.value,
                 "layout": {1: "direct", 2: "tile"}[lay.value], "stored_entries": stored.value,
-                "halo_max": hmax.value, "halo_total": htot.value, "stream_bytes": sb.value}
+                "halo_max": hmax.value, "halo_total": htot.value, "stream_bytes": sb.value,
+                "laplacian": self.laplacian}
 
     def _workspace(self, key, nbytes):
         ws = self._ws.get(key)

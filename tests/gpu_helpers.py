@@ -38,22 +38,23 @@ def power_x0(n: int, seed: int) -> np.ndarray:
     return np.random.default_rng(10_000 + seed).uniform(-1.0, 1.0, n)
 
 
-def oracle_lambda(p, iters=150):
+def oracle_lambda(p, iters=150, laplacian="normalized"):
     rp, col, w = p.graph.numpy()
-    rq, lam = c_oracle.power_max_eig(p.n, rp, col, w, power_x0(p.n, p.seed), iters)
+    rq, lam = c_oracle.power_max_eig(p.n, rp, col, w, power_x0(p.n, p.seed), iters,
+                                     laplacian=laplacian)
     return rq, lam
 
 
-def make_operator(p, store_w, layout="auto", use_order=True):
+def make_operator(p, store_w, layout="auto", use_order=True, laplacian="normalized"):
     g = p.graph
     order = getattr(p, "order", None) if use_order else None
     return gl.Operator(g.row_ptr.to(DEV), g.col.to(DEV), g.weight.to(DEV).to(torch.float64),
-                       store_w=store_w, layout=layout,
+                       store_w=store_w, layout=layout, laplacian=laplacian,
                        order=torch.from_numpy(order).to(DEV) if order is not None else None)
 
 
 def gpu_solve(p, store_w, store_u, lambda_max=2.0, outer=None, sweeps=None, u0=None,
-              labels=None, op=None, stats=True):
+              labels=None, op=None, stats=True, precond=None, step_k=None):
     outer = p.outer if outer is None else outer
     sweeps = p.sweeps if sweeps is None else sweeps
     op = op or make_operator(p, store_w)
@@ -61,9 +62,10 @@ def gpu_solve(p, store_w, store_u, lambda_max=2.0, outer=None, sweeps=None, u0=N
     labels = p.labels if labels is None else labels
     U = torch.from_numpy(np.ascontiguousarray(u0)).to(DEV, gl.TORCH_DTYPES[store_u]).contiguous()
     lab = torch.from_numpy(np.ascontiguousarray(labels, dtype=np.int32)).to(DEV)
-    st = op.solve(lab, U, eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=outer,
-                  sweeps=sweeps, delta0=p.delta0, lambda_max=lambda_max, step_k=p.step_k,
-                  stats=stats)
+    st = op.solve(lab, U, eps=p.eps, c=p.c, eta=p.eta,
+                  precond=p.precond if precond is None else precond, outer=outer,
+                  sweeps=sweeps, delta0=p.delta0, lambda_max=lambda_max,
+                  step_k=p.step_k if step_k is None else step_k, stats=stats)
     torch.cuda.synchronize()
     out = U.to(torch.float64).cpu().numpy()
     if not stats:
@@ -72,14 +74,17 @@ def gpu_solve(p, store_w, store_u, lambda_max=2.0, outer=None, sweeps=None, u0=N
     return out, e.numpy(), r.numpy(), flag, U
 
 
-def oracle_solve(p, lambda_max=2.0, outer=None, sweeps=None, u0=None, labels=None, use_c=True):
+def oracle_solve(p, lambda_max=2.0, outer=None, sweeps=None, u0=None, labels=None, use_c=True,
+                 laplacian="normalized", precond=None, step_k=None):
     rp, col, w = p.graph.numpy()
     orc = c_oracle if use_c else gl_oracle
     return orc.dca_solve(p.n, rp, col, w, p.labels if labels is None else labels,
                          p.u0 if u0 is None else u0, eps=p.eps, c=p.c, eta=p.eta,
-                         precond=p.precond, outer=p.outer if outer is None else outer,
+                         precond=p.precond if precond is None else precond,
+                         outer=p.outer if outer is None else outer,
                          sweeps=p.sweeps if sweeps is None else sweeps, delta0=p.delta0,
-                         lambda_max=lambda_max, step_k=p.step_k)
+                         lambda_max=lambda_max, step_k=p.step_k if step_k is None else step_k,
+                         laplacian=laplacian)
 
 
 def label_agreement(Ua, Ub) -> float:

@@ -57,7 +57,8 @@ def _params(**kw):
 @pytest.mark.parametrize("bad", [
     dict(eps=0.0), dict(eps=-1.0), dict(eps=math.nan), dict(c=0.0), dict(eta=-1.0),
     dict(delta0=-1e-3), dict(precond=7), dict(precond=2, lambda_max=0.0),
-    dict(precond=2, lambda_max=2.5), dict(step_k=0.0), dict(step_k=-math.inf),
+    dict(precond=2, lambda_max=math.inf), dict(precond=2, lambda_max=math.nan),
+    dict(step_k=0.0), dict(step_k=-math.inf),
     dict(step_k=math.nan), dict(outer_steps=-1), dict(inner_sweeps=0), dict(reserved=1),
 ])
 def test_params_rejected(bad):
