@@ -287,3 +287,31 @@ def assign_labels(U):
     if U.ndim == 1 or U.shape[1] == 1:
         return (U.reshape(-1) >= 0).astype(np.int32)
     return np.argmax(U, axis=1).astype(np.int32)
+
+
+# ---------------------------------------------------------------------------
+# unsupervised initialisation (Section 5.2, Table 7: the second eigenvector of
+# the normalized graph Laplacian starts the unsupervised runs)
+# ---------------------------------------------------------------------------
+
+def second_eigenpair(n, row_ptr, col, w, laplacian="normalized"):
+    """(lambda_2, v_2) of the dense Laplacian: the eigenvector of the second
+    smallest eigenvalue, unit norm, sign fixed so that its entry of largest
+    magnitude is positive (dense symmetric eigensolver; small graphs only)."""
+    if laplacian == "normalized":
+        L = dense_normalized_laplacian(n, row_ptr, col, w)
+    else:
+        L = dense_laplacian(n, row_ptr, col, w)
+    vals, vecs = np.linalg.eigh(L)
+    v = vecs[:, 1].copy()
+    i = int(np.argmax(np.abs(v)))
+    if v[i] < 0:
+        v = -v
+    return float(vals[1]), v
+
+
+def unsupervised_u0(v2):
+    """Initial field from the second eigenvector: v_2 scaled to max |u| = 1
+    (the paper does not state the scaling; this is the reading used here)."""
+    v2 = np.asarray(v2, dtype=np.float64)
+    return (v2 / np.abs(v2).max())[:, None]

@@ -552,3 +552,66 @@ def test_unnormalized_energy_decreases(orc, kind):
             want = (eps / 2) * lap + np.sum((x ** 2 - 1) ** 2) / (4 * eps) \
                 + (eta / 2) * np.sum(lam * (x - y[:, k]) ** 2)
             assert en[-1, k] == pytest.approx(want, rel=1e-12)
+
+
+# --------------------------------------------------------------------------
+# second eigenpair (unsupervised initialisation, Section 5.2)
+# --------------------------------------------------------------------------
+
+def _path(n):
+    W = np.zeros((n, n))
+    for i in range(n - 1):
+        W[i, i + 1] = W[i + 1, i] = 1.0
+    return dense_to_graph(W)
+
+
+@pytest.mark.parametrize("n", [5, 9, 16])
+def test_second_eigenpair_path_closed_form(n):
+    g = _path(n)
+    rp, col, w = g.numpy()
+    d = _dense_W(g).sum(1)
+    # L_s of the path: lambda_2 = 1 - cos(pi/(n-1)), v_2 ~ D^{1/2} cos(pi j/(n-1))
+    lam, v = gl_oracle.second_eigenpair(n, rp, col, w)
+    want = np.sqrt(d) * np.cos(np.pi * np.arange(n) / (n - 1))
+    want /= np.linalg.norm(want)
+    assert lam == pytest.approx(1 - math.cos(math.pi / (n - 1)), abs=1e-13)
+    assert abs(abs(v @ want) - 1) < 1e-12
+    # L of the path: lambda_2 = 2 - 2 cos(pi/n), v_2 ~ cos(pi (j + 1/2)/n)
+    lam, v = gl_oracle.second_eigenpair(n, rp, col, w, laplacian="unnormalized")
+    want = np.cos(np.pi * (np.arange(n) + 0.5) / n)
+    want /= np.linalg.norm(want)
+    assert lam == pytest.approx(2 - 2 * math.cos(math.pi / n), abs=1e-13)
+    assert abs(abs(v @ want) - 1) < 1e-12
+
+
+@pytest.mark.parametrize("seed", range(4))
+def test_second_eigenpair_invariants(seed):
+    rng = np.random.default_rng(300 + seed)
+    g = tiny_graph(int(rng.integers(6, 30)), 0.3, rng)
+    rp, col, w = g.numpy()
+    W = _dense_W(g)
+    d = W.sum(1)
+    lam, v = gl_oracle.second_eigenpair(g.n, rp, col, w)
+    assert np.linalg.norm(v) == pytest.approx(1.0, abs=1e-13)
+    assert abs(v @ np.sqrt(d)) < 1e-10 * np.linalg.norm(np.sqrt(d))   # v_2 _|_ D^{1/2} 1
+    np.testing.assert_allclose(_dense_Ls(W) @ v, lam * v, atol=1e-12)
+    assert v[np.argmax(np.abs(v))] > 0
+    # the smallest eigenvalue on the complement of the null vector (Courant-Fischer)
+    ev = np.linalg.eigvalsh(_dense_Ls(W))
+    assert lam == pytest.approx(ev[1], abs=1e-13)
+    u0 = gl_oracle.unsupervised_u0(v)
+    assert np.abs(u0).max() == pytest.approx(1.0)
+
+
+def test_second_eigenvector_splits_a_barbell():
+    # two 5-cliques joined by one edge: the sign of v_2 separates the cliques
+    W = np.zeros((10, 10))
+    W[:5, :5] = 1.0
+    W[5:, 5:] = 1.0
+    np.fill_diagonal(W, 0.0)
+    W[4, 5] = W[5, 4] = 1.0
+    g = dense_to_graph(W)
+    rp, col, w = g.numpy()
+    _, v = gl_oracle.second_eigenpair(10, rp, col, w)
+    s = np.sign(v)
+    assert len(set(s[:5])) == 1 and len(set(s[5:])) == 1 and s[0] != s[9]
