@@ -295,19 +295,32 @@ def assign_labels(U):
 # ---------------------------------------------------------------------------
 
 def second_eigenpair(n, row_ptr, col, w, laplacian="normalized"):
-    """(lambda_2, v_2) of the dense Laplacian: the eigenvector of the second
-    smallest eigenvalue, unit norm, sign fixed so that its entry of largest
-    magnitude is positive (dense symmetric eigensolver; small graphs only)."""
+    """(lambda_2, v_2) of the dense Laplacian, unit norm, sign fixed so that
+    its entry of largest magnitude is positive (dense symmetric eigensolver;
+    small graphs only).
+
+    The first eigenvector is the known null vector z (D^{1/2} 1 for L_s,
+    Section 2.2; 1 for L) and (lambda_2, v_2) minimises the Rayleigh quotient
+    on its orthogonal complement (Courant-Fischer), computed as the smallest
+    eigenpair of L + alpha z z^T / |z|^2 with alpha above the spectrum.  For a
+    connected graph this is the eigenvector of the second smallest eigenvalue;
+    for a disconnected one (lambda_2 = 0) it is the one null vector
+    orthogonal to z."""
     if laplacian == "normalized":
         L = dense_normalized_laplacian(n, row_ptr, col, w)
+        z = np.sqrt(degrees(n, row_ptr, col, w))
+        alpha = 3.0                                   # L_s <= 2I (Prop. 3)
     else:
         L = dense_laplacian(n, row_ptr, col, w)
-    vals, vecs = np.linalg.eigh(L)
-    v = vecs[:, 1].copy()
+        z = np.ones(n)
+        alpha = 2.0 * float(np.diag(L).max()) + 1.0   # L <= 2D (Prop. 3)
+    z = z / np.linalg.norm(z)
+    vals, vecs = np.linalg.eigh(L + alpha * np.outer(z, z))
+    v = vecs[:, 0].copy()
     i = int(np.argmax(np.abs(v)))
     if v[i] < 0:
         v = -v
-    return float(vals[1]), v
+    return float(vals[0]), v
 
 
 def unsupervised_u0(v2):

@@ -615,3 +615,27 @@ def test_second_eigenvector_splits_a_barbell():
     _, v = gl_oracle.second_eigenpair(10, rp, col, w)
     s = np.sign(v)
     assert len(set(s[:5])) == 1 and len(set(s[5:])) == 1 and s[0] != s[9]
+
+
+def test_second_eigenpair_disconnected_closed_form():
+    # two disjoint cliques A (4 nodes) and B (6 nodes): lambda_2 = 0 and v_2 is
+    # the null vector orthogonal to D^{1/2} 1: D^{1/2} (vol_B 1_A - vol_A 1_B)
+    W = np.zeros((10, 10))
+    W[:4, :4] = 1.0
+    W[4:, 4:] = 2.0
+    np.fill_diagonal(W, 0.0)
+    g = dense_to_graph(W)
+    rp, col, w = g.numpy()
+    d = W.sum(1)
+    vol_a, vol_b = d[:4].sum(), d[4:].sum()
+    want = np.sqrt(d) * np.r_[np.full(4, vol_b), np.full(6, -vol_a)]
+    want /= np.linalg.norm(want)
+    lam, v = gl_oracle.second_eigenpair(10, rp, col, w)
+    assert abs(lam) < 1e-13
+    assert abs(abs(v @ want) - 1) < 1e-12
+    # unnormalized: v_2 ~ 6 * 1_A - 4 * 1_B (orthogonal to 1)
+    lam, v = gl_oracle.second_eigenpair(10, rp, col, w, laplacian="unnormalized")
+    want = np.r_[np.full(4, 6.0), np.full(6, -4.0)]
+    want /= np.linalg.norm(want)
+    assert abs(lam) < 1e-12
+    assert abs(abs(v @ want) - 1) < 1e-12
