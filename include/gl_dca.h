@@ -196,6 +196,30 @@ gl_status gl_power_max_eig(const gl_operator *op, int32_t iters, const float *x0
                            void *workspace, size_t workspace_bytes,
                            double *rayleigh, double *lambda_hat, void *stream);
 
+/* Unsupervised initialisation (Section 5.2 starts the unsupervised runs from
+ * the second eigenvector of the normalized graph Laplacian): the second
+ * smallest eigenvalue lambda_2 of the operator's Laplacian (L_s or L) and a
+ * unit eigenvector, by Lanczos with full reorthogonalisation on the
+ * operator's own product, deflated against the null vector (D^{1/2} 1 for L_s,
+ * 1 for L), restarted from the Ritz vector until |L v - lambda_2 v| <= tol or
+ * `max_restarts` restarts have run.
+ *   krylov        Lanczos steps per restart, 2..512 (capped at n - 1)
+ *   x0            device float [n], node order: start vector, not parallel
+ *                 to the null vector
+ *   v_out         device float [n], node order: the eigenvector, unit norm,
+ *                 its entry of largest magnitude positive
+ *   *lambda2, *residual, *restarts_used (may be NULL): host outputs
+ * Vectors and products are float, inner products double.  With L_s the
+ * deflation uses the exact degrees, so weights stored in BF16/F16 leave a
+ * small null-space component; F32 weights are recommended.  Synchronises
+ * `stream`.  Errors: GL_E_INVALID_ARG (also for an x0 parallel to the null
+ * vector), GL_E_DTYPE (F64 weights), GL_E_NONFINITE (x0 zero or not finite),
+ * GL_E_HIP. */
+gl_status gl_second_eigenpair_workspace_size(const gl_operator *op, int32_t krylov, size_t *bytes);
+gl_status gl_second_eigenpair(const gl_operator *op, int32_t krylov, int32_t max_restarts, double tol,
+                              const float *x0, float *v_out, void *workspace, size_t workspace_bytes,
+                              double *lambda2, double *residual, int32_t *restarts_used, void *stream);
+
 /* Device bytes of workspace that gl_solve needs for K columns stored as
  * `store_u` (host out). */
 gl_status gl_solve_workspace_size(const gl_operator *op, int32_t K, gl_dtype store_u,

@@ -14,28 +14,6 @@
 #include "gl_layout.hpp"
 #include "gl_tile.hpp"
 
-struct gl_operator {
-    int64_t n = 0, nnz = 0, stored = 0;
-    int device = 0;
-    gl_dtype store_w = GL_F32;
-    int32_t layout = gl::LAYOUT_DIRECT;
-    bool idx64 = false;
-    int32_t* order = nullptr;   // node of each position (nullptr = natural order)
-    void* rp = nullptr;         // direct: int32/int64 offsets; tile: int32 padded offsets
-    int32_t* col = nullptr;     // direct only
-    uint16_t* lcol = nullptr;   // tile only
-    int32_t* halo = nullptr;    // tile only
-    int32_t* hp = nullptr;      // tile only
-    int32_t hmax = 0;
-    int64_t halo_total = 0, nblocks = 0;
-    void* w = nullptr;
-    double* degree = nullptr;
-    int32_t lap = GL_LAP_NORMALIZED;
-    void* dd = nullptr;   // unnormalized L: diagonal d (accumulator type, position order)
-    double dmax = 1.0;    // largest diagonal entry of the Laplacian (1 for L_s)
-    int32_t G = 16, log2G = 4, tiles = 4, remap = 1;
-    size_t bytes = 0;
-};
 
 namespace {
 
@@ -77,7 +55,9 @@ int env_int(const char* name, int dflt) {
     return (v && *v) ? std::atoi(v) : dflt;
 }
 
-gl::RowLaunch row_launch(const gl_operator* op) {
+}  // namespace
+
+gl::RowLaunch gl::operator_rows(const gl_operator* op) {
     gl::RowLaunch r = {};
     r.layout = op->layout;
     r.w = op->w;
@@ -108,6 +88,10 @@ gl::RowLaunch row_launch(const gl_operator* op) {
     r.grid = (op->n + r.rows_per_block - 1) / r.rows_per_block;
     return r;
 }
+
+namespace {
+
+gl::RowLaunch row_launch(const gl_operator* op) { return gl::operator_rows(op); }
 
 // Storage pairs the kernels are compiled for: F64 weights with an F64 field;
 // F32/BF16/F16 weights with an F32/BF16/F16 field.

@@ -48,6 +48,37 @@ struct SweepLaunch {
     double coef[14];
 };
 
+}  // namespace gl
+
+// The operator behind the gl_operator handle (library-owned device memory).
+struct gl_operator {
+    int64_t n = 0, nnz = 0, stored = 0;
+    int device = 0;
+    gl_dtype store_w = GL_F32;
+    int32_t layout = gl::LAYOUT_DIRECT;
+    bool idx64 = false;
+    int32_t* order = nullptr;   // node of each position (nullptr = natural order)
+    void* rp = nullptr;         // direct: int32/int64 offsets; tile: int32 padded offsets
+    int32_t* col = nullptr;     // direct only
+    uint16_t* lcol = nullptr;   // tile only
+    int32_t* halo = nullptr;    // tile only
+    int32_t* hp = nullptr;      // tile only
+    int32_t hmax = 0;
+    int64_t halo_total = 0, nblocks = 0;
+    void* w = nullptr;
+    double* degree = nullptr;   // d_i of the input weights, node order
+    int32_t lap = GL_LAP_NORMALIZED;
+    void* dd = nullptr;   // unnormalized L: diagonal d (accumulator type, position order)
+    double dmax = 1.0;    // largest diagonal entry of the Laplacian (1 for L_s)
+    int32_t G = 16, log2G = 4, tiles = 4, remap = 1;
+    size_t bytes = 0;
+};
+
+namespace gl {
+
+// Row-kernel launch description of an operator.
+RowLaunch operator_rows(const gl_operator* op);
+
 // Thread-local message returned by gl_last_error().
 void set_last_error(const std::string& msg);
 

@@ -103,6 +103,9 @@ SIGNATURES = {
     "gl_server_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gl_server_destroy": (ctypes.c_int, [_P]),
     "gl_knn": (ctypes.c_int, [_P, ctypes.c_int64, ctypes.c_int32, ctypes.c_int32, _P, _P, _P]),
+    "gl_second_eigenpair_workspace_size": (ctypes.c_int, [_P, ctypes.c_int32, _P]),
+    "gl_second_eigenpair": (ctypes.c_int, [_P, ctypes.c_int32, ctypes.c_int32, ctypes.c_double, _P,
+                                           _P, _P, ctypes.c_size_t, _P, _P, _P, _P]),
     "gl_last_error": (ctypes.c_char_p, []),
     "gl_version": (ctypes.c_char_p, []),
 }
@@ -250,6 +253,20 @@ class Operator:
                                     ctypes.byref(rq), ctypes.byref(lam), _stream_handle(stream)))
         return rq.value, lam.value
 
+    def second_eigenpair(self, x0: torch.Tensor, krylov: int = 64, max_restarts: int = 20,
+                         tol: float = 1e-5, stream=None):
+        """(lambda_2, v_2 [n] float, residual, restarts) of the operator's Laplacian."""
+        lib = load_library()
+        need = ctypes.c_size_t()
+        _check(lib.gl_second_eigenpair_workspace_size(self.handle, krylov, ctypes.byref(need)))
+        ws = self._workspace(("eig", krylov), need.value)
+        x0 = x0.to(torch.float32).contiguous()
+        v = torch.empty(self.n, dtype=torch.float32, device=self.device)
+        lam, res, rs = ctypes.c_double(), ctypes.c_double(), ctypes.c_int32()
+        _check(lib.gl_second_eigenpair(self.handle, krylov, max_restarts, tol, _ptr(x0), _ptr(v),
+                                       _ptr(ws), ws.numel(), ctypes.byref(lam), ctypes.byref(res),
+                                       ctypes.byref(rs), _stream_handle(stream)))
+        return lam.value, v, res.value, rs.value
     def workspace_bytes(self, K: int, store_u: str) -> int:
         nb = ctypes.c_size_t()
         _check(load_library().gl_solve_workspace_size(self._h, K, DTYPES[store_u],
