@@ -82,7 +82,12 @@ typedef enum gl_precond {
  *           columns (its halo) are staged in LDS and every entry stores a
  *           16-bit index into the halo; rows padded to 4-entry multiples.
  *           Fails with GL_E_INVALID_ARG when a halo exceeds the limit. */
-typedef enum gl_layout { GL_LAYOUT_AUTO = 0, GL_LAYOUT_DIRECT = 1, GL_LAYOUT_TILE = 2 } gl_layout;
+typedef enum gl_layout {
+    GL_LAYOUT_AUTO = 0,
+    GL_LAYOUT_DIRECT = 1,
+    GL_LAYOUT_TILE = 2,
+    GL_LAYOUT_WINDOW = 3  /* reported for operators of gl_window_operator_create; not a request */
+} gl_layout;
 
 /* Graph Laplacian of the operator (Section 2.2):
  *   NORMALIZED    L_s = I - D^{-1/2} W D^{-1/2} (the default);
@@ -151,7 +156,7 @@ typedef struct gl_operator gl_operator;
 
 /* Build the operator of `graph` (Section 2.2): validates the CSR (see
  * gl_graph), computes d_i = sum_j w_ij in F64 and stores, for L_s,
- * what_ij = w_ij / sqrt(d_i d_j) rounded to `store_w` (GL_F64, GL_F32,
+ * what_ij = w_ij / (sqrt(d_i) sqrt(d_j)) rounded to `store_w` (GL_F64, GL_F32,
  * GL_BF16 or GL_F16), for L the rounded w_ij and the row sums of the stored
  * weights as the diagonal, in library-owned device memory, with its own copy of the
  * index arrays; the caller may free `graph`'s arrays after return.  With an
@@ -160,6 +165,54 @@ typedef struct gl_operator gl_operator;
  * names the first defect), GL_E_DTYPE, GL_E_NOMEM, GL_E_HIP. */
 gl_status gl_operator_create(const gl_graph *graph, gl_dtype store_w, void *stream,
                              gl_operator **out);
+
+/* The paper's image graph (Section 2.2): pixel i is joined to every other
+ * pixel j of its search window, max(|x_i - x_j|, |y_i - y_j|) <= window_radius
+ * (the proximity N_s with dist = window_radius + 1; the 15 x 15 window is
+ * radius 7, 55 x 55 is 27), with the patch-similarity weight
+ *     w_ij = exp(-sum_n alpha_n |C(p_i + n) - C(p_j + n)|^2 / sigma^2),
+ * n over the (2 patch_radius + 1)^2 offsets of the patch (5 x 5: radius 2),
+ * C the pixel's colour vector.  The paper fixes neither alpha nor the border:
+ * here alpha_(a,b) = g(a) g(b) / (sum_t g(t))^2 with g(t) = exp(-t^2 / (2
+ * patch_radius^2)) (weights falling with the distance from the patch centre,
+ * summing to 1; alpha = 1 for patch_radius 0), and a patch position outside
+ * the image takes the colour of the nearest border pixel.
+ *   image          device float [height * width * channels]: pixel (y, x) at
+ *                  (y * width + x) * channels, channels interleaved; pixels are
+ *                  the graph's nodes in that row-major order
+ *   height, width  >= 1, height * width < 2^31
+ *   channels       1..4
+ *   window_radius  1..27;  patch_radius 0..4
+ *   sigma          finite, > 0 (the paper takes it of the order log(N) + 1)
+ *   laplacian      gl_laplacian, as in gl_graph;  reserved  0
+ */
+typedef struct gl_window_graph {
+    const float *image;
+    int32_t height;
+    int32_t width;
+    int32_t channels;
+    int32_t window_radius;
+    int32_t patch_radius;
+    int32_t laplacian;
+    double sigma;
+    int32_t reserved;
+} gl_window_graph;
+
+/* Build the operator of a window graph on the device, with implicit columns
+ * (layout GL_LAYOUT_WINDOW): the weights are computed in F64 once, the degrees
+ * d_i summed in F64 in increasing neighbour order, and the stored weights
+ * (what_ij for L_s, w_ij for L, rounded to `store_w`) kept for each pixel and
+ * window offset; neighbours outside the image store 0.  Sweeps stream
+ * (2r+1)^2 - 1 weights per pixel and no column indices.  The operator serves
+ * gl_solve, gl_laplacian_apply, gl_power_max_eig, gl_second_eigenpair and
+ * gl_time_sweeps like any other; one call with K columns needs
+ * K * (64 + 2r) * (4 + 2r) * (4 or 8 bytes) <= 65536 of LDS, checked per
+ * call (GL_E_INVALID_ARG).  Construction holds 8 bytes per stored entry of
+ * temporary device memory.  Synchronises `stream`.  Errors: GL_E_INVALID_ARG,
+ * GL_E_BAD_GRAPH (a pixel whose weights all underflow to zero: a degree of
+ * 0), GL_E_DTYPE, GL_E_NOMEM, GL_E_HIP. */
+gl_status gl_window_operator_create(const gl_window_graph *graph, gl_dtype store_w, void *stream,
+                                    gl_operator **out);
 
 /* Release an operator (waits for nothing: the caller must not destroy an
  * operator while work that uses it is still queued). NULL is accepted. */
@@ -170,9 +223,10 @@ gl_status gl_operator_destroy(gl_operator *op);
 gl_status gl_operator_info(const gl_operator *op, int64_t *n, int64_t *nnz,
                            gl_dtype *store_w, int32_t *lanes_per_row, size_t *device_bytes);
 
-/* Host: layout chosen (GL_LAYOUT_DIRECT or GL_LAYOUT_TILE), entries stored
- * (with padding), largest halo and total halo entries (tile only), and the
- * bytes of index/weight arrays one sweep streams.  Any pointer may be NULL. */
+/* Host: layout chosen (GL_LAYOUT_DIRECT, GL_LAYOUT_TILE or GL_LAYOUT_WINDOW),
+ * entries stored (with padding), largest halo and total halo entries (tile:
+ * distinct columns per block; window: staged cells per block), and the bytes
+ * of index/weight arrays one sweep streams.  Any pointer may be NULL. */
 gl_status gl_operator_layout(const gl_operator *op, int32_t *layout, int64_t *stored_entries,
                              int32_t *halo_max, int64_t *halo_total, int64_t *stream_bytes);
 

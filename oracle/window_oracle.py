@@ -19,6 +19,8 @@ itself is not its own neighbour (a full 15 x 15 window gives 224 neighbours).
 
 from __future__ import annotations
 
+import math
+
 import numpy as np
 
 
@@ -79,3 +81,51 @@ def window_graph(img: np.ndarray, rw: int, rp: int, sigma: float):
     rp_ = np.zeros(h * w + 1, dtype=np.int64)
     np.cumsum(np.bincount(rows, minlength=h * w), out=rp_[1:])
     return rp_, cols.astype(np.int32), ws
+
+
+def _patch_vectors(img: np.ndarray, rp: int) -> np.ndarray:
+    """sqrt(alpha)-weighted patch vectors of every pixel, [h, w, (2rp+1)^2 C]."""
+    h, w, _ = img.shape
+    sa = np.sqrt(patch_alpha(rp))
+    pad = np.pad(img, ((rp, rp), (rp, rp), (0, 0)), mode="edge")
+    return np.concatenate([pad[a:a + h, b:b + w, :] * sa[a, b] for a in range(2 * rp + 1)
+                           for b in range(2 * rp + 1)], axis=2)
+
+
+def window_rows(img: np.ndarray, rw: int, rp: int, sigma: float, pixels):
+    """Rows of the window graph for a few pixels of a large image, from the
+    definition, without building the whole graph: for each pixel i (row-major
+    index) returns (j ascending, w_ij, d_i, d_j)."""
+    img = np.asarray(img, dtype=np.float64)
+    if img.ndim == 2:
+        img = img[:, :, None]
+    h, w, _ = img.shape
+    out = []
+    for i in pixels:
+        yi, xi = divmod(int(i), w)
+        # every pixel within 2 rw of i (the neighbours' windows), patches from the full image
+        y0, y1 = max(yi - 2 * rw, 0), min(yi + 2 * rw, h - 1)
+        x0, x1 = max(xi - 2 * rw, 0), min(xi + 2 * rw, w - 1)
+        ys0, ys1 = max(y0 - rp, 0), min(y1 + rp, h - 1)
+        xs0, xs1 = max(x0 - rp, 0), min(x1 + rp, w - 1)
+        # patches of the crop equal the full image's when the crop keeps rp rows
+        # and columns beyond the box (or reaches the image border, replicated alike)
+        P = _patch_vectors(img[ys0:ys1 + 1, xs0:xs1 + 1], rp)[y0 - ys0:y1 - ys0 + 1,
+                                                              x0 - xs0:x1 - xs0 + 1]
+
+        dyx = np.array([(dy, dx) for dy in range(-rw, rw + 1) for dx in range(-rw, rw + 1)
+                        if dy or dx])
+
+        def weights_of(yy, xx):
+            """(neighbour ids, weights) of box pixel (yy, xx), ascending."""
+            gy, gx = yy + y0 + dyx[:, 0], xx + x0 + dyx[:, 1]
+            keep = (gy >= 0) & (gy < h) & (gx >= 0) & (gx < w)
+            gy, gx = gy[keep], gx[keep]
+            diff = P[yy, xx][None, :] - P[gy - y0, gx - x0]
+            return gy * w + gx, np.exp(-(diff * diff).sum(1) / (sigma * sigma))
+
+        js, wij = weights_of(yi - y0, xi - x0)
+        di = float(wij.sum())
+        dj = np.array([weights_of(j // w - y0, j % w - x0)[1].sum() for j in js])
+        out.append((js, wij, di, dj))
+    return out

@@ -13,6 +13,7 @@
 #include "gl_kernels.hpp"
 #include "gl_layout.hpp"
 #include "gl_tile.hpp"
+#include "gl_window.hpp"
 
 
 namespace {
@@ -65,6 +66,19 @@ gl::RowLaunch gl::operator_rows(const gl_operator* op) {
     r.order = nullptr;  // an ordered operator is renumbered: kernels index positions
     r.dd = op->dd;
     r.n = op->n;
+    if (op->layout == gl::LAYOUT_WINDOW) {
+        r.woff = op->woff;
+        r.wheight = op->wheight;
+        r.wwidth = op->wwidth;
+        r.wr = op->wr;
+        r.wM = op->wM;
+        r.wtiles_x = op->wtiles_x;
+        r.grid = op->nblocks;
+        r.rows_per_block = gl::kWinTX * gl::kWinTY;
+        r.idx64 = false;
+        r.G = 1;
+        return r;
+    }
     if (op->layout == gl::LAYOUT_TILE) {
         r.trp = (const int32_t*)op->rp;
         r.lcol = op->lcol;
@@ -98,6 +112,17 @@ gl::RowLaunch row_launch(const gl_operator* op) { return gl::operator_rows(op); 
 bool pair_ok(gl_dtype w, gl_dtype u) {
     if (w == GL_F64 || u == GL_F64) return w == GL_F64 && u == GL_F64;
     return dtype_size(w) != 0 && dtype_size(u) != 0;
+}
+
+// The window layout stages K columns of its tile's halo in LDS.
+gl_status window_fits(const gl_operator* op, int K, gl_dtype u) {
+    if (op->layout != gl::LAYOUT_WINDOW) return GL_OK;
+    const size_t need = gl::window_lds_bytes(op, K, u == GL_F64 ? 8 : 4);
+    if (need > gl::kWinLdsMax)
+        return fail(GL_E_INVALID_ARG, "window operator: K = " + std::to_string(K) + " columns need " +
+                                          std::to_string(need) + " B of LDS per block (limit " +
+                                          std::to_string(gl::kWinLdsMax) + "); use fewer columns per call");
+    return GL_OK;
 }
 
 hipError_t launch_sweep(gl_dtype u, int K, const gl::SweepLaunch& L, hipStream_t s) {
@@ -220,6 +245,7 @@ void free_op(gl_operator* op) {
     (void)hipFree(op->w);
     (void)hipFree(op->degree);
     (void)hipFree(op->dd);
+    (void)hipFree(op->woff);
     delete op;
 }
 
@@ -553,6 +579,17 @@ gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* st
                              int64_t* halo_total, int64_t* stream_bytes) {
     if (!op) return fail(GL_E_INVALID_ARG, "operator is NULL");
     const bool tile = op->layout == gl::LAYOUT_TILE;
+    if (op->layout == gl::LAYOUT_WINDOW) {
+        const int64_t cells = (int64_t)(gl::kWinTX + 2 * op->wr) * (gl::kWinTY + 2 * op->wr);
+        if (layout) *layout = GL_LAYOUT_WINDOW;
+        if (stored) *stored = op->stored;
+        if (halo_max) *halo_max = (int32_t)cells;
+        if (halo_total) *halo_total = cells * op->nblocks;
+        if (stream_bytes)
+            *stream_bytes = op->stored * (int64_t)dtype_size(op->store_w) + (int64_t)op->wM * 4 +
+                            (op->dd ? op->n * (op->store_w == GL_F64 ? 8 : 4) : 0);
+        return GL_OK;
+    }
     if (layout) *layout = tile ? GL_LAYOUT_TILE : GL_LAYOUT_DIRECT;
     if (stored) *stored = op->stored;
     if (halo_max) *halo_max = tile ? op->hmax : 0;
@@ -572,6 +609,7 @@ gl_status gl_laplacian_apply(const gl_operator* op, int32_t K, gl_dtype dtype, c
     if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
     if (!pair_ok(op->store_w, dtype)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
     if (!aligned(X, 16) || !aligned(Y, 16)) return fail(GL_E_INVALID_ARG, "X and Y must be 16-byte aligned");
+    if (window_fits(op, K, dtype) != GL_OK) return GL_E_INVALID_ARG;
     const size_t bytes = (size_t)op->n * K * dtype_size(dtype);
     const char *x = (const char*)X, *y = (const char*)Y;
     if (x < y + bytes && y < x + bytes) return fail(GL_E_INVALID_ARG, "X and Y overlap");
@@ -623,6 +661,7 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
     double* sums = (double*)(tail + 64);
 
     auto pass = [&](const float* x, float* y, int mode, const float* sc) -> hipError_t {
+        if (op->layout == gl::LAYOUT_WINDOW) return gl::launch_window_power(op, x, y, mode, sc, partials, s);
         if (op->layout == gl::LAYOUT_TILE) {
             gl::TilePowerArgs a;
             a.op.rp = (const int32_t*)op->rp;
@@ -727,6 +766,7 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
     if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
     if (!aligned(U, 16)) return fail(GL_E_INVALID_ARG, "U must be 16-byte aligned");
     if (!aligned(ws, 256)) return fail(GL_E_INVALID_ARG, "workspace must be 256-byte aligned");
+    if (window_fits(op, K, store_u) != GL_OK) return GL_E_INVALID_ARG;
     if (stats && !aligned(stats, 8)) return fail(GL_E_INVALID_ARG, "stats must be 8-byte aligned");
     size_t need = 0;
     gl_solve_workspace_size(op, K, store_u, &need);
@@ -824,6 +864,7 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     if (reps < 1 || reps > 10000) return fail(GL_E_INVALID_ARG, "reps must lie in [1, 10000]");
     if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
     if (!aligned(U, 16) || !aligned(ws, 256)) return fail(GL_E_INVALID_ARG, "U / workspace misaligned");
+    if (window_fits(op, K, store_u) != GL_OK) return GL_E_INVALID_ARG;
     size_t need = 0;
     gl_solve_workspace_size(op, K, store_u, &need);
     if (ws_bytes < need) return fail(GL_E_INVALID_ARG, "workspace too small");

@@ -10,7 +10,7 @@
 
 namespace gl {
 
-enum Layout : int32_t { LAYOUT_DIRECT = 0, LAYOUT_TILE = 1 };
+enum Layout : int32_t { LAYOUT_DIRECT = 0, LAYOUT_TILE = 1, LAYOUT_WINDOW = 2 };
 
 // Untyped description of one row-kernel launch; the unit compiled for the
 // field's storage type casts the pointers and picks the K instantiation.
@@ -34,6 +34,9 @@ struct RowLaunch {
     const int32_t* halo;
     const int32_t* hp;
     int32_t hmax;
+    // window layout (implicit columns of an image's search window)
+    const int32_t* woff;
+    int32_t wheight, wwidth, wr, wM, wtiles_x;
 };
 
 struct SweepLaunch {
@@ -71,6 +74,10 @@ struct gl_operator {
     void* dd = nullptr;   // unnormalized L: diagonal d (accumulator type, position order)
     double dmax = 1.0;    // largest diagonal entry of the Laplacian (1 for L_s)
     int32_t G = 16, log2G = 4, tiles = 4, remap = 1;
+    // window layout: image height x width, window radius, offsets per pixel,
+    // tiles per image row, LDS offset of every window offset
+    int32_t wheight = 0, wwidth = 0, wr = 0, wM = 0, wtiles_x = 0;
+    int32_t* woff = nullptr;
     size_t bytes = 0;
 };
 
@@ -78,6 +85,13 @@ namespace gl {
 
 // Row-kernel launch description of an operator.
 RowLaunch operator_rows(const gl_operator* op);
+
+// Power-method pass on the window layout (see gl::window_power_kernel).
+hipError_t launch_window_power(const gl_operator* op, const float* x, float* y, int mode, const float* scale,
+                               float* partials, hipStream_t s);
+
+// LDS bytes one window-layout block needs for K columns of accumulator size acc.
+size_t window_lds_bytes(const gl_operator* op, int K, size_t acc);
 
 // Thread-local message returned by gl_last_error().
 void set_last_error(const std::string& msg);

@@ -6,6 +6,7 @@
 #include "gl_internal.hpp"
 #include "gl_kernels.hpp"
 #include "gl_tile.hpp"
+#include "gl_window.hpp"
 
 namespace gl {
 
@@ -108,9 +109,77 @@ static hipError_t tile_laplacian_k(int K, const RowLaunch& r, const void* x, voi
     return hipGetLastError();
 }
 
+static WinOp window_op(const RowLaunch& r) {
+    WinOp op;
+    op.w = r.w;
+    op.woff = r.woff;
+    op.height = r.wheight;
+    op.width = r.wwidth;
+    op.r = r.wr;
+    op.M = r.wM;
+    op.tiles_x = r.wtiles_x;
+    return op;
+}
+
+static size_t window_lds(const RowLaunch& r, int K, size_t acc) {
+    return (size_t)K * (kWinTX + 2 * r.wr) * (kWinTY + 2 * r.wr) * acc;
+}
+
+template <typename TW, typename TU>
+static hipError_t window_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
+    typedef typename acc_of<TU>::type A;
+    WinSweepArgs<TU, A> a;
+    a.op = window_op(L.r);
+    a.ut = static_cast<const TU*>(L.ut);
+    a.vin = static_cast<const TU*>(L.vin);
+    a.vout = static_cast<TU*>(L.vout);
+    a.labels = L.labels;
+    a.dd = static_cast<const A*>(L.r.dd);
+    a.partials = static_cast<A*>(L.partials);
+    a.energy = L.energy;
+    a.k = make_sweep_args<TW, TU, int32_t>(L).k;
+    const dim3 grid((unsigned)L.r.grid), block(256);
+    const size_t lds = window_lds(L.r, K, sizeof(A));
+    switch (K) {
+#define GL_CASE(KK)                                                                         \
+    case KK:                                                                                \
+        hipLaunchKernelGGL((window_sweep_kernel<KK, TW, TU>), grid, block, lds, s, a);     \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TW, typename TU>
+static hipError_t window_laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
+    typedef typename acc_of<TU>::type A;
+    WinLapArgs<TU> a;
+    a.op = window_op(r);
+    a.x = static_cast<const TU*>(x);
+    a.y = static_cast<TU*>(y);
+    a.dd = static_cast<const A*>(r.dd);
+    const dim3 grid((unsigned)r.grid), block(256);
+    const size_t lds = window_lds(r, K, sizeof(A));
+    switch (K) {
+#define GL_CASE(KK)                                                                          \
+    case KK:                                                                                 \
+        hipLaunchKernelGGL((window_laplacian_kernel<KK, TW, TU>), grid, block, lds, s, a);  \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename TW, typename TU, typename OffT>
 static hipError_t sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
     if (L.r.layout == LAYOUT_TILE) return tile_sweep_k<TW, TU>(K, L, s);
+    if (L.r.layout == LAYOUT_WINDOW) return window_sweep_k<TW, TU>(K, L, s);
     const SweepArgs<TW, TU, OffT> a = make_sweep_args<TW, TU, OffT>(L);
     const dim3 grid((unsigned)L.r.grid), block(kBlock);
     switch (K) {
@@ -129,6 +198,7 @@ static hipError_t sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
 template <typename TW, typename TU, typename OffT>
 static hipError_t laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
     if (r.layout == LAYOUT_TILE) return tile_laplacian_k<TW, TU>(K, r, x, y, s);
+    if (r.layout == LAYOUT_WINDOW) return window_laplacian_k<TW, TU>(K, r, x, y, s);
     LapArgs<TW, TU, OffT> a;
     a.rp = static_cast<const OffT*>(r.rp);
     a.col = r.col;

@@ -41,7 +41,15 @@ class _Graph(ctypes.Structure):
                 ("layout", ctypes.c_int32), ("laplacian", ctypes.c_int32)]
 
 
+class _WindowGraph(ctypes.Structure):
+    _fields_ = [("image", ctypes.c_void_p), ("height", ctypes.c_int32), ("width", ctypes.c_int32),
+                ("channels", ctypes.c_int32), ("window_radius", ctypes.c_int32),
+                ("patch_radius", ctypes.c_int32), ("laplacian", ctypes.c_int32),
+                ("sigma", ctypes.c_double), ("reserved", ctypes.c_int32)]
+
+
 LAYOUTS = {"auto": 0, "direct": 1, "tile": 2}
+LAYOUT_NAMES = {1: "direct", 2: "tile", 3: "window"}
 LAPLACIANS = {"normalized": 0, "unnormalized": 1}
 
 
@@ -81,6 +89,7 @@ _P, _I32, _I64, _SZ, _D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctyp
                           ctypes.c_double)
 SIGNATURES = {
     "gl_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "gl_window_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "gl_operator_destroy": (ctypes.c_int, [_P]),
     "gl_operator_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gl_operator_layout": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -194,6 +203,44 @@ class Operator:
         # the library holds its own copies; drop the references
         self.row_ptr = self.col = self.weight = None
 
+    @classmethod
+    def window(cls, image: torch.Tensor, window_radius: int = 7, patch_radius: int = 2,
+               sigma: float | None = None, store_w: str = "f32", laplacian: str = "normalized",
+               stream=None) -> "Operator":
+        """Operator of the paper's image graph (Section 2.2), built on the GPU:
+        every pixel joined to its (2 window_radius + 1)^2 - 1 window neighbours
+        with patch-similarity weights over (2 patch_radius + 1)^2 patches.
+        image: CUDA float32 [h, w] or [h, w, channels], row-major pixels (the
+        nodes).  sigma defaults to log(h w) + 1."""
+        lib = load_library()
+        if not image.is_cuda:
+            raise ValueError("image must live on the GPU")
+        img = image.to(torch.float32).contiguous()
+        if img.dim() == 2:
+            img = img.unsqueeze(-1)
+        if img.dim() != 3:
+            raise ValueError("image must be [h, w] or [h, w, channels]")
+        h, w, ch = (int(v) for v in img.shape)
+        if sigma is None:
+            sigma = math.log(h * w) + 1.0
+        g = _WindowGraph(img.data_ptr(), h, w, ch, int(window_radius), int(patch_radius),
+                         LAPLACIANS[laplacian], float(sigma), 0)
+        self = cls.__new__(cls)
+        self._h = None
+        handle = ctypes.c_void_p()
+        _check(lib.gl_window_operator_create(ctypes.byref(g), DTYPES[store_w],
+                                             _stream_handle(stream), ctypes.byref(handle)))
+        self._h = handle
+        self._ws = {}
+        self.row_ptr = self.col = self.weight = None
+        self.store_w = store_w
+        self.device = image.device
+        self.laplacian = laplacian
+        self.n = h * w
+        self.nnz = self.info()["nnz"]
+        self.image_shape = (h, w)
+        return self
+
     def close(self):
         if getattr(self, "_h", None) is not None:
             load_library().gl_operator_destroy(self._h)
@@ -222,7 +269,7 @@ class Operator:
                                                  ctypes.byref(sb)))
         return {"n": n.value, "nnz": nnz.value, "lanes_per_row": lanes.value,
                 "device_bytes": by.value,
-                "layout": {1: "direct", 2: "tile"}[lay.value], "stored_entries": stored.value,
+                "layout": LAYOUT_NAMES[lay.value], "stored_entries": stored.value,
                 "halo_max": hmax.value, "halo_total": htot.value, "stream_bytes": sb.value,
                 "laplacian": self.laplacian}
 
@@ -411,6 +458,44 @@ class Server:
         _check(load_library().gl_server_info(self._h, *[ctypes.byref(x) for x in v]))
         return dict(zip(("pending", "active", "finished", "arena_used", "ticks"),
                         [x.value for x in v]))
+
+    @classmethod
+    def window(cls, image: torch.Tensor, window_radius: int = 7, patch_radius: int = 2,
+               sigma: float | None = None, store_w: str = "f32", laplacian: str = "normalized",
+               stream=None) -> "Operator":
+        """Operator of the paper's image graph (Section 2.2), built on the GPU:
+        every pixel joined to its (2 window_radius + 1)^2 - 1 window neighbours
+        with patch-similarity weights over (2 patch_radius + 1)^2 patches.
+        image: CUDA float32 [h, w] or [h, w, channels], row-major pixels (the
+        nodes).  sigma defaults to log(h w) + 1."""
+        lib = load_library()
+        if not image.is_cuda:
+            raise ValueError("image must live on the GPU")
+        img = image.to(torch.float32).contiguous()
+        if img.dim() == 2:
+            img = img.unsqueeze(-1)
+        if img.dim() != 3:
+            raise ValueError("image must be [h, w] or [h, w, channels]")
+        h, w, ch = (int(v) for v in img.shape)
+        if sigma is None:
+            sigma = math.log(h * w) + 1.0
+        g = _WindowGraph(img.data_ptr(), h, w, ch, int(window_radius), int(patch_radius),
+                         LAPLACIANS[laplacian], float(sigma), 0)
+        self = cls.__new__(cls)
+        self._h = None
+        handle = ctypes.c_void_p()
+        _check(lib.gl_window_operator_create(ctypes.byref(g), DTYPES[store_w],
+                                             _stream_handle(stream), ctypes.byref(handle)))
+        self._h = handle
+        self._ws = {}
+        self.row_ptr = self.col = self.weight = None
+        self.store_w = store_w
+        self.device = image.device
+        self.laplacian = laplacian
+        self.n = h * w
+        self.nnz = self.info()["nnz"]
+        self.image_shape = (h, w)
+        return self
 
     def close(self):
         if getattr(self, "_h", None) is not None:

@@ -190,3 +190,58 @@ def served_problem(item: StreamItem, device="cpu", knn=None) -> Problem:
                    u0=initial_u(labels, item.K), truth=comp, seed=seed, eps=100.0, c=11.0,
                    eta=100.0, precond="damped_jacobi", outer=20, sweeps=4,
                    store_w="bf16", store_u="bf16")
+
+
+# --------------------------------------------------------------------------
+# the paper's own image graph: search window + patch similarity
+# --------------------------------------------------------------------------
+
+@dataclass
+class WindowProblem:
+    """A segmentation problem on the window graph of Section 2.2, built by the
+    library from the image itself (no CSR)."""
+    name: str
+    image: np.ndarray           # float64 [h, w, 3], 8-bit colour scale
+    rw: int                     # window radius: (2 rw + 1)^2 window
+    rp: int                     # patch radius: (2 rp + 1)^2 patch
+    sigma: float
+    K: int
+    labels: np.ndarray
+    u0: np.ndarray
+    truth: np.ndarray
+    eps: float = 100.0
+    c: float = 11.0
+    eta: float = 100.0
+    precond: str = "damped_jacobi"
+    outer: int = 10
+    sweeps: int = 4
+    store_w: str = "bf16"
+    store_u: str = "f32"
+    delta0: float = 1e-6
+    step_k: float = math.inf
+    seed: int = 0
+
+    @property
+    def n(self) -> int:
+        return self.image.shape[0] * self.image.shape[1]
+
+
+def window_problem(h: int = 1024, w: int = 1024, rw: int = 12, rp: int = 2, seed: int = 5,
+                   frac: float = 0.01, nrect: int = 6, noise: float = 3.0,
+                   **kw) -> WindowProblem:
+    """Binary segmentation on the paper's window graph: `nrect` rectangles of
+    one colour over a background (colours uniform on the 8-bit scale [0, 255]^3,
+    at least 0.3 * 255 apart), Gaussian noise of `noise` levels, a fraction
+    `frac` of pixels labelled with the ground truth, sigma = log(h w) + 1 (the
+    order the paper gives for images).  Defaults: a 1024 x 1024 image with the
+    25 x 25 window and 5 x 5 patches and eps = 100, c = 11, eta = 100 and four
+    sweeps per DCA step (the paper's preconditioner comparison)."""
+    r_data, r_lab, _ = _streams(seed)
+    lo, hi = max(6, min(h, w) // 16), max(8, min(h, w) // 3)
+    img, truth = rectangles_image(h, w, nrect, r_data, side=(lo, hi), noise=noise / 255.0)
+    img *= 255.0
+    t = truth.reshape(-1).astype(np.int32)
+    labels = random_labels(t, frac, 2, r_lab)
+    return WindowProblem(name=f"window{h}x{w}-r{rw}-p{rp}", image=img, rw=rw, rp=rp,
+                         sigma=math.log(h * w) + 1.0, K=1, labels=labels,
+                         u0=initial_u(labels, 1), truth=t, seed=seed, **kw)

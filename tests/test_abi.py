@@ -99,3 +99,35 @@ def test_binding_fails_loudly_without_library(monkeypatch, tmp_path):
     monkeypatch.setattr(glmod, "_lib", None)
     with pytest.raises(RuntimeError, match="missing"):
         glmod.load_library(str(tmp_path / "nope.so"))
+
+
+def _window_graph(**kw):
+    base = dict(image=4096, height=8, width=8, channels=3, window_radius=2, patch_radius=1,
+                laplacian=0, sigma=1.0, reserved=0)
+    base.update(kw)
+    return glmod._WindowGraph(**base)
+
+
+@pytest.mark.parametrize("bad,status", [
+    (dict(image=None), 1), (dict(image=4098), 1), (dict(height=0), 1), (dict(width=-1), 1),
+    (dict(height=65536, width=32768), 1), (dict(channels=0), 1), (dict(channels=5), 1),
+    (dict(window_radius=0), 1), (dict(window_radius=28), 1), (dict(patch_radius=-1), 1),
+    (dict(patch_radius=5), 1), (dict(sigma=0.0), 1), (dict(sigma=math.inf), 1),
+    (dict(sigma=math.nan), 1), (dict(laplacian=2), 1), (dict(reserved=1), 1),
+])
+def test_window_operator_rejects_bad_arguments(bad, status):
+    lib = gl.load_library()
+    g = _window_graph(**bad)
+    out = ctypes.c_void_p()
+    assert lib.gl_window_operator_create(ctypes.byref(g), 1, None, ctypes.byref(out)) == status
+    assert out.value is None
+    assert lib.gl_last_error()
+
+
+def test_window_operator_rejects_bad_dtype_and_nulls():
+    lib = gl.load_library()
+    g = _window_graph()
+    out = ctypes.c_void_p()
+    assert lib.gl_window_operator_create(ctypes.byref(g), 9, None, ctypes.byref(out)) == 3
+    assert lib.gl_window_operator_create(None, 1, None, ctypes.byref(out)) == 1
+    assert lib.gl_window_operator_create(ctypes.byref(g), 1, None, None) == 1

@@ -82,3 +82,19 @@ def test_one_pixel_wide_and_counts():
     assert np.diff(rp_).tolist() == [2, 3, 4, 4, 4, 3, 2]
     # patch radius 0: the weight is exp(-|C_i - C_j|^2 / sigma^2)
     assert ww[rp_[0]:rp_[1]].tolist() == pytest.approx([math.exp(-1.0), math.exp(-4.0)], rel=1e-15)
+
+
+def test_window_rows_match_full_graph():
+    """The per-pixel rows (used at sizes where the full graph is too large)
+    agree with the whole graph, including the image border and the crop edge."""
+    rng = np.random.default_rng(8)
+    img = rng.uniform(0, 1, (17, 23, 3))
+    rw, rpatch, sigma = 3, 2, 0.6
+    rp_, col, ww = wo.window_graph(img, rw, rpatch, sigma)
+    d = np.add.reduceat(ww, rp_[:-1])
+    for i, (js, wij, di, dj) in zip([0, 5, 200, 23 * 8 + 11, 390],
+                                    wo.window_rows(img, rw, rpatch, sigma, [0, 5, 200, 195, 390])):
+        assert js.tolist() == col[rp_[i]:rp_[i + 1]].tolist()
+        np.testing.assert_allclose(wij, ww[rp_[i]:rp_[i + 1]], rtol=1e-13)
+        assert di == pytest.approx(d[i], rel=1e-13)
+        np.testing.assert_allclose(dj, d[js], rtol=1e-13)
