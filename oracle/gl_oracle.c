@@ -7,7 +7,7 @@
  * code with it.  The algorithm and its readings are those of gl_oracle.py:
  *
  *   Laplacian            written as diag(dd) - A (Section 2.2):
- *                        L_s = I - D^{-1/2} W D^{-1/2}: A_ij = w_ij / sqrt(d_i d_j), dd = 1;
+ *                        L_s = I - D^{-1/2} W D^{-1/2}: A_ij = w_ij / (sqrt(d_i) sqrt(d_j)), dd = 1;
  *                        L   = D - W:                   A = W,                      dd = d;
  *                        d_i = sum_j w_ij
  *   DCA right-hand side  b = c u - (u^3 - u)/eps + eta Lambda y      (Prop. 1)
@@ -52,7 +52,7 @@ static int operator_parts(int64_t n, const int64_t *rp, const int32_t *col, cons
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; i++)
             for (int64_t p = rp[i]; p < rp[i + 1]; p++)
-                A[p] = w[p] / sqrt(d[i] * d[col[p]]);
+                A[p] = w[p] / (sqrt(d[i]) * sqrt(d[col[p]]));
 #pragma omp parallel for schedule(static)
         for (int64_t i = 0; i < n; i++) d[i] = 1.0;
     }

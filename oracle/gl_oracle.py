@@ -54,7 +54,7 @@ def normalized_weights(n, row_ptr, col, w):
     if np.any(d <= 0):
         raise ValueError("every degree must be positive")
     rows = np.repeat(np.arange(n), np.diff(row_ptr))
-    return w / np.sqrt(d[rows] * d[col.astype(np.int64)])
+    return w / (np.sqrt(d[rows]) * np.sqrt(d[col.astype(np.int64)]))
 
 
 def normalized_adjacency(n, row_ptr, col, w):

@@ -362,7 +362,7 @@ __global__ void degree_kernel(int64_t n, const int64_t* __restrict__ rp, const T
     }
 }
 
-// what_ij = w_ij / sqrt(d_i d_j) in double, rounded once to TOUT; the index
+// what_ij = w_ij / (sqrt(d_i) sqrt(d_j)) in double, rounded once to TOUT; the index
 // arrays are copied (row offsets narrowed to OffT) in the same pass.
 // raw != 0 (unnormalized L = D - W): w_ij itself, rounded once to TOUT.
 template <typename TIN, typename TOUT, typename OffT>
@@ -378,7 +378,7 @@ __global__ void normalize_kernel(int64_t n, const int64_t* __restrict__ rp, cons
     for (int64_t p = rp[i]; p < rp[i + 1]; ++p) {
         const int32_t j = col[p];
         col_out[p] = j;
-        w_out[p] = store_as<TOUT>::from(raw ? (double)w[p] : (double)w[p] / sqrt(di * d[j]));
+        w_out[p] = store_as<TOUT>::from(raw ? (double)w[p] : (double)w[p] / (sqrt(di) * sqrt(d[j])));
     }
 }
 

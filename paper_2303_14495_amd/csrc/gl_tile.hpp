@@ -393,7 +393,7 @@ __global__ __launch_bounds__(256) void tile_power_kernel(TilePowerArgs a) {
 }
 
 // Fill the tile (or direct) weight array: entry e of position p takes the
-// normalized weight of source entry src[e] (w / sqrt(d_i d_j), i the node of p),
+// normalized weight of source entry src[e] (w / (sqrt(d_i) sqrt(d_j)), i the node of p),
 // or 0 when src[e] < 0 (padding).  col_out (direct layout only) receives the
 // source column, mapped through pos_of (node -> position) when ordered.
 // raw != 0 (unnormalized L = D - W): the weight itself, rounded once.
@@ -411,7 +411,7 @@ __global__ void fill_layout_kernel(int64_t n, const int32_t* __restrict__ rp_out
         const int32_t s = src[e];
         if (s >= 0) {
             const int32_t j = col[s];
-            w_out[e] = store_as<TOUT>::from(raw ? (double)w[s] : (double)w[s] / sqrt(di * d[j]));
+            w_out[e] = store_as<TOUT>::from(raw ? (double)w[s] : (double)w[s] / (sqrt(di) * sqrt(d[j])));
             if (col_out) col_out[e] = pos_of ? pos_of[j] : j;
         } else {
             w_out[e] = store_as<TOUT>::from(0.0);
