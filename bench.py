@@ -34,9 +34,10 @@ DSIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_sweep_image2048_k4_traffic.json")
 # sources whose change invalidates recorded counter traffic of the sweep kernel
+WINDOW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_sweep_1024_r12_traffic.json")  # + _<weights>
 TRAFFIC_SOURCES = ["gl_tile.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
                    "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_f16.hip",
-                   "gl_api.hip"]
+                   "gl_unit_f32.hip", "gl_window.hpp", "gl_api.hip"]
 
 
 def sweep_source_hash():
@@ -48,13 +49,13 @@ def sweep_source_hash():
     return h.hexdigest()
 
 
-def recorded_traffic(workload_name, storage):
+def recorded_traffic(workload_name, storage, path=TRAFFIC_FILE):
     """HBM bytes per sweep launch from the committed counter summary (FETCH_SIZE
     and WRITE_SIZE of the sweep kernel, each scaled by what the counter reads
     for a 1 GiB elementwise copy), or None when the summary is missing, is for
     another workload or storage, or predates the current kernel sources."""
     try:
-        with open(TRAFFIC_FILE) as fh:
+        with open(path) as fh:
             t = json.load(fh)
     except (OSError, ValueError):
         return None
@@ -381,7 +382,10 @@ def window_bench(dev, steps, warmup, reps):
                         "frac_of_hbm_peak": B / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
                         "weight_build_ms": t_build * 1e3, "nnz": info["nnz"],
                         "stored_entries": info["stored_entries"],
-                        "kernel": f"window_sweep_kernel<1, {store_w}, f32>"}
+                        "kernel": f"window_sweep_kernel<1, {store_w}, f32>",
+                        "traffic": recorded_traffic(p.name, f"{store_w}/f32",
+                                                    WINDOW_TRAFFIC_FILE.replace(
+                                                        ".json", f"_{store_w}.json"))}
         op.close()
         del U, U0, Uf
         torch.cuda.empty_cache()

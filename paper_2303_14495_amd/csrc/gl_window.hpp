@@ -96,7 +96,9 @@ __device__ __forceinline__ void window_products(const WinOp& op, const TU* __res
     for (int k = 0; k < K; ++k) z0[k] = z1[k] = (A)0;
 #pragma unroll 4
     for (int g = 0; g < ng; ++g) {
-        const u32x4 wq = wp[(int64_t)g * 256];
+        // streamed once per sweep: a non-temporal load keeps the weights from
+        // evicting the V halos that neighbouring tiles re-read from L2
+        const u32x4 wq = __builtin_nontemporal_load(wp + (int64_t)g * 256);
         TW we[GS];
         __builtin_memcpy(we, &wq, 16);
 #pragma unroll
