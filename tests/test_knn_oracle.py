@@ -1,10 +1,13 @@
 """Pins of the kNN oracle: closed-form neighbour lists on a line and a
 lattice (with exact ties), and agreement with SciPy's k-d tree."""
 
+import math
+
 import numpy as np
 import pytest
 
 from oracle import knn_oracle
+from oracle import knn_oracle as ko
 
 
 def test_line_closed_form():
@@ -50,3 +53,54 @@ def test_rows_subset_and_self_excluded():
     sub_i, sub_d = knn_oracle.knn(x, 5, rows=rows)
     assert np.array_equal(full_i[rows], sub_i) and np.array_equal(full_d[rows], sub_d)
     assert not np.any(full_i == np.arange(300)[:, None])
+
+
+def test_graph_from_knn_line_by_hand():
+    """Points 0, 1, 3, 7 on a line, k = 2, bandwidth from the nearest
+    neighbour: lists, scales, union and weights worked out by hand."""
+    x = np.array([[0.0], [1.0], [3.0], [7.0]])
+    idx, d2 = ko.knn(x, 2)
+    assert idx.tolist() == [[1, 2], [0, 2], [1, 0], [2, 1]]
+    rp, col, w = ko.graph_from_knn(4, idx, d2, scale_rank=1)
+    # s = (1, 1, 2, 4)
+    want = {(0, 1): math.exp(-1.0), (0, 2): math.exp(-9 / 2), (1, 2): math.exp(-4 / 2),
+            (2, 3): math.exp(-16 / 8), (1, 3): math.exp(-36 / 4)}
+    assert rp.tolist() == [0, 2, 5, 8, 10]
+    assert col.tolist() == [1, 2, 0, 2, 3, 0, 1, 3, 1, 2]
+    for i in range(4):
+        for p in range(rp[i], rp[i + 1]):
+            j = int(col[p])
+            assert w[p] == pytest.approx(want[(min(i, j), max(i, j))], rel=1e-15)
+
+
+def test_graph_from_knn_invariants():
+    rng = np.random.default_rng(3)
+    x = rng.standard_normal((300, 5))
+    idx, d2 = ko.knn(x, 8)
+    rp, col, w = ko.graph_from_knn(300, idx, d2, scale_rank=4)
+    W = np.zeros((300, 300))
+    for i in range(300):
+        W[i, col[rp[i]:rp[i + 1]]] = w[rp[i]:rp[i + 1]]
+    np.testing.assert_array_equal(W, W.T)          # symmetric
+    assert np.all(np.diag(W) == 0)                  # no self-loops
+    assert np.all((W == 0) | ((W > 0) & (W <= 1)))  # weights in (0, 1]
+    # union: every kNN edge is present, and every edge comes from a kNN list
+    E = W > 0
+    K = np.zeros_like(E)
+    K[np.repeat(np.arange(300), 8), idx.ravel()] = True
+    assert np.array_equal(E, K | K.T)
+    # the bandwidth: the weight of i's scale_rank-th neighbour j is exp(-s_i / s_j)
+    s = np.sqrt(d2[:, 3])
+    for i in range(0, 300, 37):
+        j = idx[i, 3]
+        assert W[i, j] == pytest.approx(math.exp(-s[i] / s[j]), rel=1e-13)
+
+
+def test_graph_from_knn_duplicates_and_underflow():
+    # four identical points: their scales are 0 (floored), mutual weights exp(0) = 1;
+    # a far point keeps only edges whose weight does not underflow
+    x = np.array([[0.0], [0.0], [0.0], [0.0], [1e3]])
+    idx, d2 = ko.knn(x, 2)
+    rp, col, w = ko.graph_from_knn(5, idx, d2, scale_rank=1)
+    assert np.all(w[:rp[4]] == 1.0)
+    assert rp[5] - rp[4] == 0  # the far point's weights underflow: isolated
