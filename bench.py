@@ -37,7 +37,7 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_sweep_image2048_k4_traffic.j
 WINDOW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_sweep_1024_r12_traffic.json")  # + _<weights>
 TRAFFIC_SOURCES = ["gl_tile.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
                    "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_f16.hip",
-                   "gl_unit_f32.hip", "gl_window.hpp", "gl_api.hip"]
+                   "gl_unit_f32.hip", "gl_window.hpp", "gl_grid.hpp", "gl_api.hip"]
 
 
 def sweep_source_hash():
@@ -84,6 +84,8 @@ def parse():
     ap.add_argument("--sweep-reps", type=int, default=40)
     ap.add_argument("--no-served", action="store_true", help="skip the served stream")
     ap.add_argument("--no-window", action="store_true", help="skip the window-graph run")
+    ap.add_argument("--no-grid", action="store_true",
+                    help="image workloads: tile layout in Z-order instead of the grid layout")
     ap.add_argument("--window-only", action="store_true")
     ap.add_argument("--served-only", action="store_true")
     ap.add_argument("--served-count", type=int, default=256)
@@ -399,6 +401,33 @@ def window_bench(dev, steps, warmup, reps):
     return out
 
 
+def knn_graph_bench(dev):
+    """Graph construction on the GPU (exact kNN, then the union-symmetric
+    graph with local-scaling weights): 262 144 points in R^10 from a
+    5-component mixture, k = 10, bandwidth from the 7th neighbour."""
+    import numpy as np
+    import torch
+    import paper_2303_14495_amd as gl
+    rng = np.random.default_rng(31)
+    n, d, k = 262144, 10, 10
+    means = 3.0 * rng.standard_normal((5, d))
+    x = (means[rng.integers(0, 5, n)] + rng.standard_normal((n, d))).astype(np.float32)
+    xt = torch.from_numpy(x).to(dev)
+    idx, d2 = gl.knn(xt, k)  # warm-up
+    gl.knn_graph(idx, d2, 7)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    idx, d2 = gl.knn(xt, k)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    rp, col, w = gl.knn_graph(idx, d2, 7)
+    torch.cuda.synchronize()
+    t2 = time.perf_counter()
+    return {"points": n, "dim": d, "k": k, "scale_rank": 7, "knn_ms": (t1 - t0) * 1e3,
+            "graph_ms": (t2 - t1) * 1e3, "nnz": int(col.numel()),
+            "knn_pair_rate_per_s": n * (n - 1) / (t1 - t0)}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -426,6 +455,8 @@ def main():
     log(f"  {p.name}: n={p.n} nnz={p.graph.nnz} K={p.K} ({time.perf_counter() - t:.1f} s)")
     g = p.graph
     order = torch.from_numpy(p.order).to(dev) if p.order is not None else None
+    # image graphs: the grid layout (one-byte window-relative columns)
+    grid = p.extra.get("grid") if not args.no_grid else None
     labels = torch.from_numpy(p.labels).to(dev)
     x0 = torch.from_numpy(np.random.default_rng(10_000 + p.seed).uniform(-1, 1, p.n)).to(
         dev, torch.float32)
@@ -433,7 +464,10 @@ def main():
     def run_variant(store_w, store_u, steps, warmup):
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        op = gl.Operator(g.row_ptr, g.col, g.weight, store_w=store_w, order=order)
+        if grid is not None:
+            op = gl.Operator(g.row_ptr, g.col, g.weight, store_w=store_w, layout="grid", grid=grid)
+        else:
+            op = gl.Operator(g.row_ptr, g.col, g.weight, store_w=store_w, order=order)
         torch.cuda.synchronize()
         t_create = time.perf_counter() - t0
         lam = 2.0
@@ -523,6 +557,11 @@ def main():
             f"({window['bf16']['sweep_gbps']:.0f} GB/s), f32 sweep "
             f"{window['f32']['sweep_kernel_ms'] * 1e3:.1f} us ({window['f32']['sweep_gbps']:.0f} GB/s)")
 
+    log("kNN graph construction")
+    kg = knn_graph_bench(dev)
+    log(f"  {kg['points']} points: kNN {kg['knn_ms']:.1f} ms, graph {kg['graph_ms']:.1f} ms, "
+        f"nnz {kg['nnz']}")
+
     served = None
     if not args.no_served:
         served = served_bench(dev, args.served_count, args.served_rate, args.served_budget_gib,
@@ -558,13 +597,15 @@ def main():
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBPS,
                      "unit": "GB/s", "frac": achieved / HBM_PEAK_GBPS,
                      "traffic": recorded_traffic(p.name, f"{sw}/{su}"),
-                     "kernel": f"tile_sweep_kernel<{p.K}, {sw}, {su}>"
-                               if main_res["layout"] == "tile" else "sweep_kernel",
+                     "kernel": {"tile": f"tile_sweep_kernel<{p.K}, {sw}, {su}>",
+                                "grid": f"grid_sweep_kernel<{p.K}, {sw}, {su}>"}.get(
+                                    main_res["layout"], "sweep_kernel"),
                      "bytes_per_launch": B},
         "cpu_baseline": cpu,
         "served": served,
         "unsupervised": unsup,
         "window_graph": window,
+        "knn_graph": kg,
     }
     print(json.dumps(out), flush=True)
     if args.calib_copy:

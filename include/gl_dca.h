@@ -86,7 +86,8 @@ typedef enum gl_layout {
     GL_LAYOUT_AUTO = 0,
     GL_LAYOUT_DIRECT = 1,
     GL_LAYOUT_TILE = 2,
-    GL_LAYOUT_WINDOW = 3  /* reported for operators of gl_window_operator_create; not a request */
+    GL_LAYOUT_WINDOW = 3, /* reported for operators of gl_window_operator_create; not a request */
+    GL_LAYOUT_GRID = 4    /* nodes are the pixels of a grid_height x grid_width image (see gl_graph) */
 } gl_layout;
 
 /* Graph Laplacian of the operator (Section 2.2):
@@ -114,6 +115,17 @@ typedef enum gl_laplacian { GL_LAP_NORMALIZED = 0, GL_LAP_UNNORMALIZED = 1 } gl_
  *            (their workspaces grow accordingly).
  *   layout   gl_layout request.
  *   laplacian gl_laplacian: L_s or L.
+ *   grid_height, grid_width  for GL_LAYOUT_GRID: node i is the pixel
+ *            (i / grid_width, i % grid_width) of an image (n = height *
+ *            width) and every edge joins pixels at most 7 rows and 7 columns
+ *            apart (within the paper's default 15 x 15 search window, Section
+ *            2.2); 0 otherwise.  The grid layout stores, per pixel, its
+ *            entries as one byte of window offset (dy, dx) and the weight, in
+ *            chunks of 8, and stages each 64 x 8 pixel tile's 15 x 15 window
+ *            halo of the field in LDS; it takes no `order` and is built on
+ *            the host (the CSR pattern is copied back once).  One call with K
+ *            columns needs K * 78 * 22 * (4 or 8 bytes) <= 65536 of LDS,
+ *            checked per call.
  * Every degree d_i = sum_j w_ij must be > 0. */
 typedef struct gl_graph {
     int64_t n;
@@ -125,6 +137,8 @@ typedef struct gl_graph {
     const int32_t *order;
     int32_t layout;
     int32_t laplacian;
+    int32_t grid_height;
+    int32_t grid_width;
 } gl_graph;
 
 /* Solver parameters (Section 3 and Section 3.1).
@@ -223,9 +237,9 @@ gl_status gl_operator_destroy(gl_operator *op);
 gl_status gl_operator_info(const gl_operator *op, int64_t *n, int64_t *nnz,
                            gl_dtype *store_w, int32_t *lanes_per_row, size_t *device_bytes);
 
-/* Host: layout chosen (GL_LAYOUT_DIRECT, GL_LAYOUT_TILE or GL_LAYOUT_WINDOW),
+/* Host: layout chosen (GL_LAYOUT_DIRECT, GL_LAYOUT_TILE, GL_LAYOUT_WINDOW or GL_LAYOUT_GRID),
  * entries stored (with padding), largest halo and total halo entries (tile:
- * distinct columns per block; window: staged cells per block), and the bytes
+ * distinct columns per block; window, grid: staged cells per block), and the bytes
  * of index/weight arrays one sweep streams.  Any pointer may be NULL. */
 gl_status gl_operator_layout(const gl_operator *op, int32_t *layout, int64_t *stored_entries,
                              int32_t *halo_max, int64_t *halo_total, int64_t *stream_bytes);
@@ -249,6 +263,30 @@ gl_status gl_power_workspace_size(const gl_operator *op, size_t *bytes);
 gl_status gl_power_max_eig(const gl_operator *op, int32_t iters, const float *x0,
                            void *workspace, size_t workspace_bytes,
                            double *rayleigh, double *lambda_hat, void *stream);
+
+/* The clustering graph of Section 2.2 from kNN lists (e.g. gl_knn's): i and
+ * j are joined when either is among the other's k nearest neighbours (N_c,
+ * symmetrised by union), with the local-scaling Gaussian weight of
+ * Zelnik-Manor and Perona
+ *     w_ij = exp(-|x_i - x_j|^2 / (s_i s_j)),  s_i = sqrt(d2[i][scale_rank-1])
+ * (s_i = 2^-256 when that distance is 0), computed in F64.  Edges whose
+ * weight is 0 are left out.
+ *   idx       device int32 [n x k], each row ascending by distance, no self
+ *   d2        device float [n x k], squared distances; symmetric (|x_i-x_j|^2
+ *             computed alike from both ends, as gl_knn does); when an edge is
+ *             in both lists the lower row's entry is used
+ *   row_ptr   device int64 [n+1] (out);  col device int32, weight device
+ *             double [capacity] (out, first *nnz entries; columns ascending per
+ *             row, no self-loops): a gl_graph ready for gl_operator_create
+ *   capacity  >= 2 n k;  *nnz (host out)
+ * 2 <= n < 2^31, 1 <= k <= min(n-1, 1024), 2 n k < 2^31, 1 <= scale_rank <= k.
+ * Allocates about 48 n k bytes of stream-ordered temporaries; synchronises
+ * `stream`.  Errors: GL_E_INVALID_ARG (also an index out of range or equal
+ * to its row, a negative or non-finite distance), GL_E_BAD_GRAPH (a point
+ * whose weights are all 0), GL_E_NOMEM, GL_E_HIP. */
+gl_status gl_knn_graph(int64_t n, int32_t k, const int32_t *idx, const float *d2, int32_t scale_rank,
+                       int64_t *row_ptr, int32_t *col, double *weight, int64_t capacity, int64_t *nnz,
+                       void *stream);
 
 /* Unsupervised initialisation (Section 5.2 starts the unsupervised runs from
  * the second eigenvector of the normalized graph Laplacian): the second

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgl_dca.so")
-SOURCES = ["gl_api.hip", "gl_layout.hip", "gl_server.hip", "gl_knn.hip", "gl_eigen.hip", "gl_window.hip", "gl_unit_f64.hip", "gl_unit_f32.hip",
+SOURCES = ["gl_api.hip", "gl_layout.hip", "gl_server.hip", "gl_knn.hip", "gl_eigen.hip", "gl_window.hip", "gl_graph.hip", "gl_unit_f64.hip", "gl_unit_f32.hip",
            "gl_unit_bf16.hip", "gl_unit_f16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"

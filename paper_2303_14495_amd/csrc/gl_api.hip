@@ -14,6 +14,7 @@
 #include "gl_layout.hpp"
 #include "gl_tile.hpp"
 #include "gl_window.hpp"
+#include "gl_grid.hpp"
 
 
 namespace {
@@ -66,6 +67,19 @@ gl::RowLaunch gl::operator_rows(const gl_operator* op) {
     r.order = nullptr;  // an ordered operator is renumbered: kernels index positions
     r.dd = op->dd;
     r.n = op->n;
+    if (op->layout == gl::LAYOUT_GRID) {
+        r.goffs = op->goffs;
+        r.gwbase = op->gwbase;
+        r.gcnt = op->gcnt;
+        r.wheight = op->wheight;
+        r.wwidth = op->wwidth;
+        r.wtiles_x = op->wtiles_x;
+        r.grid = op->nblocks;
+        r.rows_per_block = gl::kGridThreads;
+        r.idx64 = false;
+        r.G = 1;
+        return r;
+    }
     if (op->layout == gl::LAYOUT_WINDOW) {
         r.woff = op->woff;
         r.wheight = op->wheight;
@@ -116,6 +130,14 @@ bool pair_ok(gl_dtype w, gl_dtype u) {
 
 // The window layout stages K columns of its tile's halo in LDS.
 gl_status window_fits(const gl_operator* op, int K, gl_dtype u) {
+    if (op->layout == gl::LAYOUT_GRID) {
+        const size_t need = (size_t)K * gl::kGridCells * (u == GL_F64 ? 8 : 4);
+        if (need > gl::kGridLdsMax)
+            return fail(GL_E_INVALID_ARG, "grid operator: K = " + std::to_string(K) + " columns need " +
+                                              std::to_string(need) + " B of LDS per block (limit " +
+                                              std::to_string(gl::kGridLdsMax) + "); use fewer columns per call");
+        return GL_OK;
+    }
     if (op->layout != gl::LAYOUT_WINDOW) return GL_OK;
     const size_t need = gl::window_lds_bytes(op, K, u == GL_F64 ? 8 : 4);
     if (need > gl::kWinLdsMax)
@@ -246,6 +268,9 @@ void free_op(gl_operator* op) {
     (void)hipFree(op->degree);
     (void)hipFree(op->dd);
     (void)hipFree(op->woff);
+    (void)hipFree(op->goffs);
+    (void)hipFree(op->gwbase);
+    (void)hipFree(op->gcnt);
     delete op;
 }
 
@@ -272,18 +297,41 @@ hipError_t launch_rowsum(gl_operator* op, hipStream_t s) {
     return hipGetLastError();
 }
 
-gl_status finish_unnormalized(gl_operator* op, hipStream_t s) {
+// Grid layout: the same row sums, taken over the input CSR rows (whose order
+// is the storage order) with every weight rounded as stored.
+template <typename TW, typename A>
+hipError_t launch_grid_rowsum(gl_operator* op, const gl_graph* g, hipStream_t s) {
+    const unsigned grid = (unsigned)((op->n + 255) / 256);
+    if (g->weight_dtype == GL_F64)
+        hipLaunchKernelGGL((gl::grid_rowsum_kernel<double, TW, A>), dim3(grid), dim3(256), 0, s, op->n, g->row_ptr,
+                           (const double*)g->weight, (A*)op->dd);
+    else
+        hipLaunchKernelGGL((gl::grid_rowsum_kernel<float, TW, A>), dim3(grid), dim3(256), 0, s, op->n, g->row_ptr,
+                           (const float*)g->weight, (A*)op->dd);
+    return hipGetLastError();
+}
+
+gl_status finish_unnormalized(gl_operator* op, hipStream_t s, const gl_graph* g = nullptr) {
     if (op->lap != GL_LAP_UNNORMALIZED) return GL_OK;
     const size_t es = op->store_w == GL_F64 ? 8 : 4;
     if (hipMalloc(&op->dd, (size_t)op->n * es) != hipSuccess)
         return fail(GL_E_NOMEM, "device allocation for the operator failed");
     op->bytes += (size_t)op->n * es;
     hipError_t e = hipSuccess;
-    switch (op->store_w) {
-        case GL_F64: e = launch_rowsum<double, double>(op, s); break;
-        case GL_F32: e = launch_rowsum<float, float>(op, s); break;
-        case GL_BF16: e = launch_rowsum<gl::bf16, float>(op, s); break;
-        default: e = launch_rowsum<gl::f16, float>(op, s); break;
+    if (op->layout == gl::LAYOUT_GRID) {
+        switch (op->store_w) {
+            case GL_F64: e = launch_grid_rowsum<double, double>(op, g, s); break;
+            case GL_F32: e = launch_grid_rowsum<float, float>(op, g, s); break;
+            case GL_BF16: e = launch_grid_rowsum<gl::bf16, float>(op, g, s); break;
+            default: e = launch_grid_rowsum<gl::f16, float>(op, g, s); break;
+        }
+    } else {
+        switch (op->store_w) {
+            case GL_F64: e = launch_rowsum<double, double>(op, s); break;
+            case GL_F32: e = launch_rowsum<float, float>(op, s); break;
+            case GL_BF16: e = launch_rowsum<gl::bf16, float>(op, s); break;
+            default: e = launch_rowsum<gl::f16, float>(op, s); break;
+        }
     }
     std::vector<char> h((size_t)op->n * es);
     if (e == hipSuccess) e = hipMemcpyAsync(h.data(), op->dd, h.size(), hipMemcpyDeviceToHost, s);
@@ -372,10 +420,17 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     if (g->weight_dtype != GL_F64 && g->weight_dtype != GL_F32)
         return fail(GL_E_DTYPE, "input weights must be GL_F64 or GL_F32");
     if (dtype_size(store_w) == 0) return fail(GL_E_DTYPE, "unknown store_w");
-    if (g->layout < GL_LAYOUT_AUTO || g->layout > GL_LAYOUT_TILE) return fail(GL_E_INVALID_ARG, "unknown layout");
+    if (!(g->layout >= GL_LAYOUT_AUTO && g->layout <= GL_LAYOUT_TILE) && g->layout != GL_LAYOUT_GRID)
+        return fail(GL_E_INVALID_ARG, "unknown layout");
+    const bool grid_req = g->layout == GL_LAYOUT_GRID;
+    if (grid_req) {
+        if (g->grid_height < 1 || g->grid_width < 1 || (int64_t)g->grid_height * g->grid_width != g->n)
+            return fail(GL_E_INVALID_ARG, "the grid layout needs grid_height * grid_width == n");
+        if (g->order) return fail(GL_E_INVALID_ARG, "the grid layout takes no order");
+    }
     if (g->laplacian != GL_LAP_NORMALIZED && g->laplacian != GL_LAP_UNNORMALIZED)
         return fail(GL_E_INVALID_ARG, "unknown laplacian");
-    const bool host_layout = g->order != nullptr || g->layout == GL_LAYOUT_TILE;
+    const bool host_layout = g->order != nullptr || g->layout == GL_LAYOUT_TILE || grid_req;
     if (host_layout && g->nnz > (int64_t)INT32_MAX)
         return fail(GL_E_INVALID_ARG, "an order or the tile layout needs nnz < 2^31");
     hipStream_t s = (hipStream_t)stream;
@@ -500,6 +555,65 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
             seen[i] = 1;
         }
     }
+    if (grid_req) {
+        gl::GridLayout GLy;
+        std::string gerr;
+        if (!gl::build_grid_layout(g->n, g->grid_height, g->grid_width, h_rp.data(), h_col.data(), GLy, gerr))
+            return cleanup_fail(GL_E_INVALID_ARG, gerr);
+        h_col.clear();
+        h_col.shrink_to_fit();
+        op->layout = gl::LAYOUT_GRID;
+        op->idx64 = false;
+        op->G = 1;
+        op->wheight = g->grid_height;
+        op->wwidth = g->grid_width;
+        op->wtiles_x = GLy.tiles_x;
+        op->nblocks = (int64_t)GLy.tiles_x * ((g->grid_height + gl::kGridTY - 1) / gl::kGridTY);
+        op->gchunks = GLy.chunks;
+        op->stored = GLy.chunks * gl::kGridChunk;
+        hipError_t e = upload(&d_src, GLy.src, s);
+        std::vector<uint64_t> offs64((size_t)GLy.chunks);
+        if (GLy.chunks) std::memcpy(offs64.data(), GLy.offs.data(), (size_t)GLy.chunks * 8);
+        GLy.offs.clear();
+        GLy.offs.shrink_to_fit();
+        if (e == hipSuccess) e = upload(&op->goffs, offs64, s);
+        if (e == hipSuccess) e = upload(&op->gwbase, GLy.wbase, s);
+        if (e == hipSuccess) e = upload(&op->gcnt, GLy.cnt, s);
+        if (e == hipSuccess) e = hipMalloc(&op->w, (size_t)op->stored * sw + 64);
+        if (e == hipSuccess) e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
+        op->bytes = (size_t)op->stored * sw + (size_t)GLy.chunks * 8 + GLy.wbase.size() * 8 + (size_t)g->n +
+                    (size_t)g->n * 8;
+        const unsigned gs = (unsigned)((op->stored + 255) / 256);
+        const int raw = op->lap == GL_LAP_UNNORMALIZED ? 1 : 0;
+        auto fill = [&](auto tin, auto tout) {
+            typedef decltype(tin) TIN;
+            typedef decltype(tout) TOUT;
+            hipLaunchKernelGGL((gl::grid_fill_kernel<TIN, TOUT>), dim3(gs), dim3(256), 0, s, op->stored, g->n,
+                               g->row_ptr, g->col_idx, (const TIN*)g->weight, op->degree, d_src, (TOUT*)op->w, raw);
+        };
+        auto fill_in = [&](auto tin) {
+            switch (store_w) {
+                case GL_F64: fill(tin, double{}); break;
+                case GL_F32: fill(tin, float{}); break;
+                case GL_BF16: fill(tin, gl::bf16{}); break;
+                default: fill(tin, gl::f16{}); break;
+            }
+        };
+        if (g->weight_dtype == GL_F64) fill_in(double{});
+        else fill_in(float{});
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return cleanup_fail(GL_E_HIP, "weight normalization failed");
+        const gl_status su = finish_unnormalized(op, s, g);
+        if (su != GL_OK) {
+            const std::string m = gl_last_error();
+            return cleanup_fail(su, m);
+        }
+        (void)hipFree(d_src);
+        (void)hipFree(scratch);
+        *out = op;
+        return GL_OK;
+    }
     gl::HostLayout L;
     std::string err;
     const int32_t halo_limit = store_w == GL_F64 ? 480 : gl::kTileHaloMax;
@@ -579,6 +693,17 @@ gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* st
                              int64_t* halo_total, int64_t* stream_bytes) {
     if (!op) return fail(GL_E_INVALID_ARG, "operator is NULL");
     const bool tile = op->layout == gl::LAYOUT_TILE;
+    if (op->layout == gl::LAYOUT_GRID) {
+        if (layout) *layout = GL_LAYOUT_GRID;
+        if (stored) *stored = op->stored;
+        if (halo_max) *halo_max = gl::kGridCells;
+        if (halo_total) *halo_total = (int64_t)gl::kGridCells * op->nblocks;
+        if (stream_bytes)
+            *stream_bytes = op->gchunks * (8 + 8 * (int64_t)dtype_size(op->store_w)) + op->n +
+                            (int64_t)op->wheight * op->wtiles_x * 8 +
+                            (op->dd ? op->n * (op->store_w == GL_F64 ? 8 : 4) : 0);
+        return GL_OK;
+    }
     if (op->layout == gl::LAYOUT_WINDOW) {
         const int64_t cells = (int64_t)(gl::kWinTX + 2 * op->wr) * (gl::kWinTY + 2 * op->wr);
         if (layout) *layout = GL_LAYOUT_WINDOW;
@@ -662,6 +787,31 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
 
     auto pass = [&](const float* x, float* y, int mode, const float* sc) -> hipError_t {
         if (op->layout == gl::LAYOUT_WINDOW) return gl::launch_window_power(op, x, y, mode, sc, partials, s);
+        if (op->layout == gl::LAYOUT_GRID) {
+            gl::GridPowerArgs a;
+            a.op.w = op->w;
+            a.op.offs = op->goffs;
+            a.op.wbase = op->gwbase;
+            a.op.cnt = op->gcnt;
+            a.op.height = op->wheight;
+            a.op.width = op->wwidth;
+            a.op.tiles_x = op->wtiles_x;
+            a.x = x;
+            a.y = y;
+            a.scale = sc;
+            a.partials = partials;
+            a.dd = (const float*)op->dd;
+            a.mode = mode;
+            const size_t lds = (size_t)gl::kGridCells * 4;
+            const dim3 gg((unsigned)r.grid), bb(gl::kGridThreads);
+            switch (op->store_w) {
+                case GL_F32: hipLaunchKernelGGL(gl::grid_power_kernel<float>, gg, bb, lds, s, a); break;
+                case GL_BF16: hipLaunchKernelGGL(gl::grid_power_kernel<gl::bf16>, gg, bb, lds, s, a); break;
+                case GL_F16: hipLaunchKernelGGL(gl::grid_power_kernel<gl::f16>, gg, bb, lds, s, a); break;
+                default: return hipErrorInvalidValue;
+            }
+            return hipGetLastError();
+        }
         if (op->layout == gl::LAYOUT_TILE) {
             gl::TilePowerArgs a;
             a.op.rp = (const int32_t*)op->rp;

@@ -1,0 +1,329 @@
+// Grid layout: a sparse graph on the pixels of an image whose edges stay
+// within the 15 x 15 search window (Section 2.2), with window-relative
+// one-byte columns.
+//
+// Entry (i, j) stores the byte (dy + 7) << 4 | (dx + 7), where (dy, dx) is
+// pixel j's offset from pixel i, and its weight.  A pixel's entries, in CSR
+// order, form chunks of 8 (the last one padded with the byte 0x77, the pixel
+// itself, and weight 0, so padding needs no branch).  Work mapping: a block of
+// 512 lanes owns a 64 x 8 pixel tile, one pixel per lane and one image row per
+// wavefront; the block stages V over the tile and its 7-pixel halo in LDS,
+// K values per cell side by side (one vector LDS read per entry), zeros
+// outside the image.  Chunks are stored so that every wavefront load is
+// contiguous: within a wavefront (a 64-pixel row segment), chunk c of all
+// lanes that have more than c chunks follows chunk c - 1 of all lanes, in
+// lane order; a lane finds its chunk from the wavefront's first chunk, a
+// ballot of the lanes still active and a population count.  A sweep thus
+// streams 3 bytes per entry in BF16/F16 (1 + 2), plus padding, and no row
+// offsets or halo lists.
+#pragma once
+
+#include "gl_kernels.hpp"
+
+namespace gl {
+
+constexpr int kGridTX = 64;                       // tile width: one wavefront per image row
+constexpr int kGridTY = 8;                        // tile height: eight wavefronts
+constexpr int kGridThreads = kGridTX * kGridTY;   // 512
+constexpr int kGridR = 7;                         // window radius (15 x 15)
+constexpr int kGridS = kGridTX + 2 * kGridR;      // staged row length, 78
+constexpr int kGridHY = kGridTY + 2 * kGridR;     // staged rows, 22
+constexpr int kGridCells = kGridS * kGridHY;      // 1716
+constexpr int kGridChunk = 8;                     // entries per chunk
+constexpr uint8_t kGridPad = 0x77;                // offset byte of the pixel itself
+constexpr size_t kGridLdsMax = 65536;
+
+struct GridOp {
+    const void* w;          // [chunks][8] weights
+    const uint64_t* offs;   // [chunks] 8 offset bytes
+    const int64_t* wbase;   // [height * tiles_x] first chunk of each wavefront
+    const uint8_t* cnt;     // [n] chunks per pixel
+    int32_t height, width, tiles_x;
+};
+
+// Fixed-order block reduction of per-lane column statistics for NW wavefronts
+// (as block_stats, every lane holding all K columns).
+template <int K, int NW, typename A>
+__device__ __forceinline__ void block_stats_lanes(A (&e)[K], A (&r)[K], A* __restrict__ partials, int64_t nb,
+                                                  int64_t b) {
+    __shared__ A sh[NW][2][K];
+    for (int off = 1; off < 64; off <<= 1) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            e[k] += __shfl_xor(e[k], off, 64);
+            r[k] += __shfl_xor(r[k], off, 64);
+        }
+    }
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    if (lane == 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            sh[wave][0][k] = e[k];
+            sh[wave][1][k] = r[k];
+        }
+    }
+    __syncthreads();
+    if (threadIdx.x < 2 * K) {
+        const int kind = threadIdx.x / K, k = threadIdx.x - kind * K;
+        A s = sh[0][kind][k];
+#pragma unroll
+        for (int w = 1; w < NW; ++w) s += sh[w][kind][k];
+        partials[(int64_t)threadIdx.x * nb + b] = s;
+    }
+}
+
+// Z = W V for the lane's pixel; the pixel's own V row comes from the staged tile.
+//   prefetch(ok, p): issue the loads of the pixel's own data
+//   finish(ok, p, z, v): consume the product
+template <int K, typename TW, typename TU, typename A, typename Pre, typename Fin>
+__device__ __forceinline__ void grid_products(const GridOp& op, const TU* __restrict__ V, int64_t b, A* hv,
+                                              Pre&& prefetch, Fin&& finish) {
+    constexpr int NV = kGridChunk * (int)sizeof(TW) / 16;  // 16-byte vectors per chunk
+    const int ty = (int)(b / op.tiles_x), tx = (int)(b - (int64_t)ty * op.tiles_x);
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const int x = tx * kGridTX + lane, y = ty * kGridTY + wave;
+    const bool ok = x < op.width && y < op.height;
+    const int64_t p = (int64_t)y * op.width + x;
+    const int cnt = ok ? (int)op.cnt[p] : 0;
+    const int64_t wb = y < op.height ? op.wbase[(int64_t)y * op.tiles_x + tx] : 0;
+    prefetch(ok, p);
+
+    // stage V over the tile and its halo: every lane loads its 4 cells from
+    // clamped (always valid) addresses, all in flight at once, and zeroes the
+    // cells outside the image afterwards
+    const int gx0 = tx * kGridTX - kGridR, gy0 = ty * kGridTY - kGridR;
+    for (int c0 = 0; c0 < kGridCells; c0 += 4 * kGridThreads) {
+        A vals[4][K];
+        bool in[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kGridThreads + (int)threadIdx.x;
+            const int cc = c < kGridCells ? c : kGridCells - 1;
+            const int hy = cc / kGridS, hx = cc - hy * kGridS;
+            const int gy = gy0 + hy, gx = gx0 + hx;
+            in[u] = gy >= 0 && gy < op.height && gx >= 0 && gx < op.width;
+            const int gyc = gy < 0 ? 0 : (gy >= op.height ? op.height - 1 : gy);
+            const int gxc = gx < 0 ? 0 : (gx >= op.width ? op.width - 1 : gx);
+            load_row<K>(V + ((int64_t)gyc * op.width + gxc) * K, vals[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const int c = c0 + u * kGridThreads + (int)threadIdx.x;
+            if (c < kGridCells) {
+#pragma unroll
+                for (int k = 0; k < K; ++k) hv[c * K + k] = in[u] ? vals[u][k] : (A)0;
+            }
+        }
+    }
+    __syncthreads();
+
+    int maxc = cnt;
+    for (int off = 32; off > 0; off >>= 1) maxc = max(maxc, __shfl_xor(maxc, off, 64));
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int rowbase = wave * kGridS + lane;  // staged cell of window offset (-7, -7)
+    const u32x4* wv4 = static_cast<const u32x4*>(op.w);
+    int64_t next = wb;
+    A z[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = (A)0;
+    constexpr int U = 2;  // chunks in flight per lane
+    for (int c = 0; c < maxc; c += U) {
+        uint64_t ob[U];
+        u32x4 wq[U][NV];
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool act = c + u < cnt;
+            const uint64_t m = __ballot(act);
+            const int64_t id = next + __popcll(m & below);
+            next += __popcll(m);
+            if (act) {
+                // streamed once per sweep: keep the staged V halos of other tiles in L2
+                ob[u] = __builtin_nontemporal_load(op.offs + id);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) wq[u][v] = __builtin_nontemporal_load(wv4 + id * NV + v);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            if (c + u < cnt) {
+                TW we[kGridChunk];
+                __builtin_memcpy(we, &wq[u][0], sizeof(we));
+#pragma unroll
+                for (int e = 0; e < kGridChunk; ++e) {
+                    const uint32_t byte = (uint32_t)(ob[u] >> (8 * e)) & 0xffu;
+                    const int at = rowbase + (int)(byte >> 4) * kGridS + (int)(byte & 15u);
+                    const A w = cvt<A>(we[e]);
+                    A hvv[K];
+                    constexpr int kAl = (K * sizeof(A)) % 16 == 0 ? 16 : (K * sizeof(A)) % 8 == 0 ? 8 : 4;
+                    __builtin_memcpy(hvv, __builtin_assume_aligned(&hv[at * K], kAl), sizeof(hvv));
+#pragma unroll
+                    for (int k = 0; k < K; ++k) z[k] += w * hvv[k];
+                }
+            }
+        }
+    }
+    const int center = (wave + kGridR) * kGridS + lane + kGridR;
+    A vc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) vc[k] = hv[center * K + k];
+    finish(ok, p, z, vc);
+}
+
+template <typename TU, typename A> struct GridSweepArgs {
+    GridOp op;
+    const TU* ut;
+    const TU* vin;
+    TU* vout;  // nullptr: energy-only pass
+    const int32_t* labels;
+    const A* dd;  // d_i of L = D - W, or nullptr for L_s
+    A* partials;
+    int32_t energy;
+    SweepCoef<A> k;
+};
+
+// One sweep (or the energy-only pass) on the grid layout; the update is the
+// one of sweep_block, for all K columns of the lane's pixel.
+template <int K, typename TW, typename TU>
+__global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<TU, typename acc_of<TU>::type> a) {
+    typedef typename acc_of<TU>::type A;
+    extern __shared__ unsigned char smem_raw[];
+    A* hv = reinterpret_cast<A*>(smem_raw);
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    int32_t lab = -1;
+    A dl = (A)1;
+    A uu[K], e_acc[K], r_acc[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) uu[k] = e_acc[k] = r_acc[k] = (A)0;
+    auto prefetch = [&](bool ok, int64_t p) {
+        if (!ok) return;
+        lab = a.labels[p];
+        if (a.dd) dl = a.dd[p];
+        load_row<K>(a.ut + p * K, uu);
+    };
+    auto finish = [&](bool ok, int64_t p, const A (&z)[K], const A (&vc)[K]) {
+        if (!ok) return;
+        const A lam = lab >= 0 ? (A)1 : (A)0;
+        const A ginv = a.dd ? (A)1 / (a.k.ga + a.k.gd * dl + a.k.gl * lam) : (lab >= 0 ? a.k.ginv1 : a.k.ginv0);
+#pragma unroll
+        for (int k = 0; k < K; ++k) {
+            const A zk = z[k], u = uu[k], v = vc[k];
+            const A y = lab < 0 ? (A)0 : (K == 1 ? (lab == 1 ? (A)1 : (A)-1) : (lab == k ? (A)1 : (A)-1));
+            const A rhs = a.k.c * u - (u * u * u - u) * a.k.inv_eps + a.k.eta * lam * y;
+            const A lv = a.dd ? dl * v - zk : v - zk;
+            const A tv = a.k.eps * lv + (a.k.eta * lam + a.k.c) * v;
+            const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
+            if (a.vout) a.vout[p * K + k] = store_as<TU>::from(v + r * ginv);
+            r_acc[k] += r * r;
+            if (a.energy) {
+                const A u2m1 = u * u - (A)1, dy = u - y;
+                const A ulu = fma_acc(u, a.dd ? dl * u : u, -(u * zk));  // u (L u)_i, one rounding
+                e_acc[k] += a.k.half_eps * ulu + a.k.quarter_inv_eps * u2m1 * u2m1 + a.k.half_eta * lam * dy * dy;
+            }
+        }
+    };
+    grid_products<K, TW, TU, A>(a.op, a.vin, b, hv, prefetch, finish);
+    if (a.partials) block_stats_lanes<K, kGridTY>(e_acc, r_acc, a.partials, (int64_t)gridDim.x, b);
+}
+
+// Y = X - What X (L_s X) or D X - W X (L X) on the grid layout
+template <typename TU> struct GridLapArgs {
+    GridOp op;
+    const TU* x;
+    TU* y;
+    const typename acc_of<TU>::type* dd;
+};
+
+template <int K, typename TW, typename TU>
+__global__ __launch_bounds__(kGridThreads) void grid_laplacian_kernel(GridLapArgs<TU> a) {
+    typedef typename acc_of<TU>::type A;
+    extern __shared__ unsigned char smem_raw[];
+    A* hv = reinterpret_cast<A*>(smem_raw);
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    A dl = (A)1;
+    auto prefetch = [&](bool ok, int64_t p) {
+        if (ok && a.dd) dl = a.dd[p];
+    };
+    auto finish = [&](bool ok, int64_t p, const A (&z)[K], const A (&vc)[K]) {
+        if (!ok) return;
+#pragma unroll
+        for (int k = 0; k < K; ++k) a.y[p * K + k] = store_as<TU>::from((a.dd ? dl * vc[k] : vc[k]) - z[k]);
+    };
+    grid_products<K, TW, TU, A>(a.op, a.x, b, hv, prefetch, finish);
+}
+
+// Power-method pass on the grid layout (float vectors; see power_kernel).
+struct GridPowerArgs {
+    GridOp op;
+    const float* x;
+    float* y;
+    const float* scale;
+    float* partials;
+    const float* dd;
+    int32_t mode;
+};
+
+template <typename TW>
+__global__ __launch_bounds__(kGridThreads) void grid_power_kernel(GridPowerArgs a) {
+    extern __shared__ unsigned char smem_raw[];
+    float* hv = reinterpret_cast<float*>(smem_raw);
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const float s = a.mode == 0 ? *a.scale : 1.0f;
+    float dl = 1.f, p0 = 0.f, p1 = 0.f;
+    auto prefetch = [&](bool ok, int64_t p) {
+        if (ok && a.dd) dl = a.dd[p];
+    };
+    auto finish = [&](bool ok, int64_t p, const float (&z)[1], const float (&vc)[1]) {
+        if (!ok) return;
+        const float xv = vc[0];
+        const float lx = (a.dd ? dl * xv : xv) - z[0];
+        if (a.mode == 0) {
+            const float yv = s * lx;
+            a.y[p] = yv;
+            p0 += yv * yv;
+        } else {
+            p0 += xv * lx;
+            p1 += xv * xv;
+        }
+    };
+    grid_products<1, TW, float, float>(a.op, a.x, b, hv, prefetch, finish);
+    float e[1] = {p0}, r[1] = {p1};
+    block_stats_lanes<1, kGridTY>(e, r, a.partials, (int64_t)gridDim.x, b);
+}
+
+// Grid layout weights: slot s takes the weight of CSR entry src[s]
+// (w / (sqrt(d_i) sqrt(d_j)) for L_s, w itself for L, rounded once), or 0 for
+// padding (src[s] < 0).  The row i of an entry is found by binary search.
+template <typename TIN, typename TOUT>
+__global__ void grid_fill_kernel(int64_t slots, int64_t n, const int64_t* __restrict__ rp,
+                                 const int32_t* __restrict__ col, const TIN* __restrict__ w,
+                                 const double* __restrict__ d, const int32_t* __restrict__ src,
+                                 TOUT* __restrict__ w_out, int32_t raw) {
+    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (s >= slots) return;
+    const int32_t e = src[s];
+    if (e < 0) {
+        w_out[s] = store_as<TOUT>::from(0.0);
+        return;
+    }
+    int64_t lo = 0, hi = n;  // last row with rp[row] <= e
+    while (hi - lo > 1) {
+        const int64_t mid = (lo + hi) >> 1;
+        if (rp[mid] <= e) lo = mid; else hi = mid;
+    }
+    const double wv = (double)w[e];
+    w_out[s] = store_as<TOUT>::from(raw ? wv : wv / (sqrt(d[lo]) * sqrt(d[col[e]])));
+}
+
+// Unnormalized L on the grid layout: dd_i = sum over row i of the weights as
+// stored (rounded to TW), in CSR order (the storage order), summed in double.
+template <typename TIN, typename TW, typename A>
+__global__ void grid_rowsum_kernel(int64_t n, const int64_t* __restrict__ rp, const TIN* __restrict__ w,
+                                   A* __restrict__ dd) {
+    const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= n) return;
+    double s = 0.0;
+    for (int64_t e = rp[i]; e < rp[i + 1]; ++e) s += cvt<double>(store_as<TW>::from((double)w[e]));
+    dd[i] = (A)s;
+}
+
+}  // namespace gl

@@ -10,7 +10,7 @@
 
 namespace gl {
 
-enum Layout : int32_t { LAYOUT_DIRECT = 0, LAYOUT_TILE = 1, LAYOUT_WINDOW = 2 };
+enum Layout : int32_t { LAYOUT_DIRECT = 0, LAYOUT_TILE = 1, LAYOUT_WINDOW = 2, LAYOUT_GRID = 3 };
 
 // Untyped description of one row-kernel launch; the unit compiled for the
 // field's storage type casts the pointers and picks the K instantiation.
@@ -37,6 +37,11 @@ struct RowLaunch {
     // window layout (implicit columns of an image's search window)
     const int32_t* woff;
     int32_t wheight, wwidth, wr, wM, wtiles_x;
+    // grid layout (window-relative one-byte columns); image size and tiles_x
+    // share wheight, wwidth, wtiles_x
+    const uint64_t* goffs;
+    const int64_t* gwbase;
+    const uint8_t* gcnt;
 };
 
 struct SweepLaunch {
@@ -78,6 +83,12 @@ struct gl_operator {
     // tiles per image row, LDS offset of every window offset
     int32_t wheight = 0, wwidth = 0, wr = 0, wM = 0, wtiles_x = 0;
     int32_t* woff = nullptr;
+    // grid layout: offset bytes, first chunk per row segment, chunks per pixel
+    // (image size and tiles per row in wheight, wwidth, wtiles_x)
+    uint64_t* goffs = nullptr;
+    int64_t* gwbase = nullptr;
+    uint8_t* gcnt = nullptr;
+    int64_t gchunks = 0;
     size_t bytes = 0;
 };
 

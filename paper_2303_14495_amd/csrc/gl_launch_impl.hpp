@@ -7,6 +7,7 @@
 #include "gl_kernels.hpp"
 #include "gl_tile.hpp"
 #include "gl_window.hpp"
+#include "gl_grid.hpp"
 
 namespace gl {
 
@@ -176,8 +177,72 @@ static hipError_t window_laplacian_k(int K, const RowLaunch& r, const void* x, v
     return hipGetLastError();
 }
 
+static GridOp grid_op(const RowLaunch& r) {
+    GridOp op;
+    op.w = r.w;
+    op.offs = r.goffs;
+    op.wbase = r.gwbase;
+    op.cnt = r.gcnt;
+    op.height = r.wheight;
+    op.width = r.wwidth;
+    op.tiles_x = r.wtiles_x;
+    return op;
+}
+
+template <typename TW, typename TU>
+static hipError_t grid_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
+    typedef typename acc_of<TU>::type A;
+    GridSweepArgs<TU, A> a;
+    a.op = grid_op(L.r);
+    a.ut = static_cast<const TU*>(L.ut);
+    a.vin = static_cast<const TU*>(L.vin);
+    a.vout = static_cast<TU*>(L.vout);
+    a.labels = L.labels;
+    a.dd = static_cast<const A*>(L.r.dd);
+    a.partials = static_cast<A*>(L.partials);
+    a.energy = L.energy;
+    a.k = make_sweep_args<TW, TU, int32_t>(L).k;
+    const dim3 grid((unsigned)L.r.grid), block(kGridThreads);
+    const size_t lds = (size_t)K * kGridCells * sizeof(A);
+    switch (K) {
+#define GL_CASE(KK)                                                                       \
+    case KK:                                                                              \
+        hipLaunchKernelGGL((grid_sweep_kernel<KK, TW, TU>), grid, block, lds, s, a);     \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <typename TW, typename TU>
+static hipError_t grid_laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
+    typedef typename acc_of<TU>::type A;
+    GridLapArgs<TU> a;
+    a.op = grid_op(r);
+    a.x = static_cast<const TU*>(x);
+    a.y = static_cast<TU*>(y);
+    a.dd = static_cast<const A*>(r.dd);
+    const dim3 grid((unsigned)r.grid), block(kGridThreads);
+    const size_t lds = (size_t)K * kGridCells * sizeof(A);
+    switch (K) {
+#define GL_CASE(KK)                                                                        \
+    case KK:                                                                               \
+        hipLaunchKernelGGL((grid_laplacian_kernel<KK, TW, TU>), grid, block, lds, s, a);  \
+        break;
+        GL_K_CASES(GL_CASE)
+#undef GL_CASE
+        default:
+            return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
 template <typename TW, typename TU, typename OffT>
 static hipError_t sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
+    if (L.r.layout == LAYOUT_GRID) return grid_sweep_k<TW, TU>(K, L, s);
     if (L.r.layout == LAYOUT_TILE) return tile_sweep_k<TW, TU>(K, L, s);
     if (L.r.layout == LAYOUT_WINDOW) return window_sweep_k<TW, TU>(K, L, s);
     const SweepArgs<TW, TU, OffT> a = make_sweep_args<TW, TU, OffT>(L);
@@ -199,6 +264,7 @@ template <typename TW, typename TU, typename OffT>
 static hipError_t laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
     if (r.layout == LAYOUT_TILE) return tile_laplacian_k<TW, TU>(K, r, x, y, s);
     if (r.layout == LAYOUT_WINDOW) return window_laplacian_k<TW, TU>(K, r, x, y, s);
+    if (r.layout == LAYOUT_GRID) return grid_laplacian_k<TW, TU>(K, r, x, y, s);
     LapArgs<TW, TU, OffT> a;
     a.rp = static_cast<const OffT*>(r.rp);
     a.col = r.col;

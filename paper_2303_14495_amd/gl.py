@@ -38,7 +38,8 @@ class _Graph(ctypes.Structure):
     _fields_ = [("n", ctypes.c_int64), ("nnz", ctypes.c_int64), ("row_ptr", ctypes.c_void_p),
                 ("col_idx", ctypes.c_void_p), ("weight", ctypes.c_void_p),
                 ("weight_dtype", ctypes.c_int32), ("order", ctypes.c_void_p),
-                ("layout", ctypes.c_int32), ("laplacian", ctypes.c_int32)]
+                ("layout", ctypes.c_int32), ("laplacian", ctypes.c_int32),
+                ("grid_height", ctypes.c_int32), ("grid_width", ctypes.c_int32)]
 
 
 class _WindowGraph(ctypes.Structure):
@@ -48,8 +49,8 @@ class _WindowGraph(ctypes.Structure):
                 ("sigma", ctypes.c_double), ("reserved", ctypes.c_int32)]
 
 
-LAYOUTS = {"auto": 0, "direct": 1, "tile": 2}
-LAYOUT_NAMES = {1: "direct", 2: "tile", 3: "window"}
+LAYOUTS = {"auto": 0, "direct": 1, "tile": 2, "grid": 4}
+LAYOUT_NAMES = {1: "direct", 2: "tile", 3: "window", 4: "grid"}
 LAPLACIANS = {"normalized": 0, "unnormalized": 1}
 
 
@@ -90,6 +91,7 @@ _P, _I32, _I64, _SZ, _D = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctyp
 SIGNATURES = {
     "gl_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "gl_window_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
+    "gl_knn_graph": (ctypes.c_int, [_I64, _I32, _P, _P, _I32, _P, _P, _P, _I64, _P, _P]),
     "gl_operator_destroy": (ctypes.c_int, [_P]),
     "gl_operator_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gl_operator_layout": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -172,7 +174,7 @@ class Operator:
     """
 
     def __init__(self, row_ptr, col, weight, store_w: str = "f32", stream=None, order=None,
-                 layout: str = "auto", laplacian: str = "normalized"):
+                 layout: str = "auto", laplacian: str = "normalized", grid=None):
         lib = load_library()
         if not (row_ptr.is_cuda and col.is_cuda and weight.is_cuda):
             raise ValueError("graph tensors must live on the GPU")
@@ -192,7 +194,7 @@ class Operator:
         g = _Graph(self.n, self.nnz, self.row_ptr.data_ptr(), self.col.data_ptr(),
                    self.weight.data_ptr(), DTYPES[DTYPE_OF_TORCH[weight.dtype]],
                    order_t.data_ptr() if order_t is not None else None, LAYOUTS[layout],
-                   LAPLACIANS[laplacian])
+                   LAPLACIANS[laplacian], *((0, 0) if grid is None else (int(grid[0]), int(grid[1]))))
         self.laplacian = laplacian
         handle = ctypes.c_void_p()
         self._h = None
@@ -359,6 +361,25 @@ def time_sweeps(op: Operator, labels: torch.Tensor, U: torch.Tensor, *, eps, c, 
                               _ptr(U), _ptr(ws), ws.numel(), reps, ctypes.byref(out),
                               _stream_handle(stream)))
     return out.value
+
+
+def knn_graph(idx: torch.Tensor, d2: torch.Tensor, scale_rank: int = 7, stream=None):
+    """Union-symmetric kNN graph with local-scaling weights (Section 2.2) from
+    kNN lists on the GPU: returns (row_ptr int64 [n+1], col int32 [nnz],
+    weight float64 [nnz]) CUDA tensors."""
+    idx = idx.to(torch.int32).contiguous()
+    d2 = d2.to(torch.float32).contiguous()
+    n, k = (int(v) for v in idx.shape)
+    cap = 2 * n * k
+    row_ptr = torch.empty(n + 1, dtype=torch.int64, device=idx.device)
+    col = torch.empty(cap, dtype=torch.int32, device=idx.device)
+    w = torch.empty(cap, dtype=torch.float64, device=idx.device)
+    nnz = ctypes.c_int64()
+    _check(load_library().gl_knn_graph(n, k, _ptr(idx), _ptr(d2), int(scale_rank), _ptr(row_ptr),
+                                       _ptr(col), _ptr(w), cap, ctypes.byref(nnz),
+                                       _stream_handle(stream)))
+    m = nnz.value
+    return row_ptr, col[:m].clone(), w[:m].clone()
 
 
 def assign_labels(U: torch.Tensor, stream=None) -> torch.Tensor:

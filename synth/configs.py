@@ -89,7 +89,7 @@ def _image_problem(name, img, truth, k, frac, K, seed, r_lab, device, **kw):
     t = truth.reshape(-1).astype(np.int32)
     labels = random_labels(t, frac, max(K, 2), r_lab)
     return Problem(name=name, graph=g, K=K, labels=labels, u0=initial_u(labels, K),
-                   truth=t, seed=seed, order=zorder(h, w), **kw)
+                   truth=t, seed=seed, order=zorder(h, w), extra={"grid": (h, w)}, **kw)
 
 
 def make_problem(cfg: int, device="cpu", small: bool = False) -> Problem:

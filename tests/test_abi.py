@@ -131,3 +131,27 @@ def test_window_operator_rejects_bad_dtype_and_nulls():
     assert lib.gl_window_operator_create(ctypes.byref(g), 9, None, ctypes.byref(out)) == 3
     assert lib.gl_window_operator_create(None, 1, None, ctypes.byref(out)) == 1
     assert lib.gl_window_operator_create(ctypes.byref(g), 1, None, None) == 1
+
+
+@pytest.mark.parametrize("n,k,rank,cap,status", [
+    (1, 1, 1, 2, 1), (10, 0, 1, 20, 1), (10, 10, 1, 200, 1), (10, 3, 0, 60, 1),
+    (10, 3, 4, 60, 1), (10, 3, 2, 59, 1), (1 << 31, 3, 2, 6 << 31, 1),
+])
+def test_knn_graph_rejects_bad_sizes(n, k, rank, cap, status):
+    lib = gl.load_library()
+    fake = ctypes.c_void_p(4096)
+    nnz = ctypes.c_int64()
+    assert lib.gl_knn_graph(n, k, fake, fake, rank, fake, fake, fake, cap, ctypes.byref(nnz),
+                            None) == status
+    assert lib.gl_last_error()
+
+
+def test_knn_graph_rejects_nulls():
+    lib = gl.load_library()
+    fake = ctypes.c_void_p(4096)
+    nnz = ctypes.c_int64()
+    args = [10, 3, fake, fake, 2, fake, fake, fake, 60, ctypes.byref(nnz), None]
+    for pos in (2, 3, 5, 6, 7, 9):
+        a = list(args)
+        a[pos] = None
+        assert lib.gl_knn_graph(*a) == 1

@@ -106,3 +106,80 @@ def test_knn_rejects_bad_sizes():
             gl.knn(x, k)
     with pytest.raises(gl.GLError):
         gl.knn(torch.zeros((10, 65), device=DEV), 3)
+
+
+# ---------------------------------------------------------------------------
+# gl_knn_graph: union-symmetric graph with local-scaling weights
+# ---------------------------------------------------------------------------
+
+def _graph_gpu(idx, d2, scale_rank):
+    rp, col, w = gl.knn_graph(torch.from_numpy(np.ascontiguousarray(idx)).to(DEV),
+                              torch.from_numpy(np.ascontiguousarray(d2)).to(DEV), scale_rank)
+    return rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+
+
+@pytest.mark.parametrize("n,d,k,rank", [(1500, 6, 10, 7), (3000, 10, 20, 7), (257, 3, 1, 1)])
+def test_knn_graph_assembly_matches_oracle(n, d, k, rank):
+    """Same kNN lists on both sides (the oracle's, distances rounded to float32):
+    the edge sets must be identical and the weights agree to rounding."""
+    x = mixture(n, d, n + k).astype(np.float64)
+    idx, d2 = knn_oracle.knn(x, k)
+    d2f = d2.astype(np.float32)
+    say(f"knn graph assembly n={n} k={k} rank={rank}")
+    rp, col, w = _graph_gpu(idx.astype(np.int32), d2f, rank)
+    orp, ocol, ow = knn_oracle.graph_from_knn(n, idx, d2f.astype(np.float64), rank)
+    assert rp.tolist() == orp.tolist()
+    assert col.tolist() == ocol.tolist()
+    assert np.abs(w - ow).max() <= 1e-14 * max(1.0, ow.max())
+
+
+def test_knn_graph_end_to_end_vs_oracle():
+    """gl_knn (float32) then gl_knn_graph against the oracle's recipe in
+    float64.  Rows whose k-th and (k+1)-th oracle neighbours are clearly apart
+    must pick the oracle's list; near-tie rows may pick either point, so the
+    oracle graph is built from the GPU's lists with float64 distances: the edge
+    sets must then be identical and the weights agree to float32 rounding."""
+    n, d, k, rank = 2000, 8, 12, 7
+    x = mixture(n, d, 99)
+    xd = x.astype(np.float64)
+    oi, od = knn_oracle.knn(xd, k + 1)
+    idx, d2 = gl.knn(torch.from_numpy(x).to(DEV), k)
+    gi = idx.cpu().numpy()
+    clear = (od[:, k] - od[:, k - 1]) / od[:, k] > 1e-5
+    assert np.array_equal(gi[clear], oi[clear, :k])
+    rp, col, w = gl.knn_graph(idx, d2, rank)
+    rp, col, w = rp.cpu().numpy(), col.cpu().numpy(), w.cpu().numpy()
+    true_d2 = ((xd[:, None, :] - xd[gi]) ** 2).sum(-1)
+    orp, ocol, ow = knn_oracle.graph_from_knn(n, gi, true_d2, rank)
+    assert rp.tolist() == orp.tolist() and col.tolist() == ocol.tolist()
+    rel = np.abs(w - ow) / ow
+    say(f"knn graph end to end: nnz {len(col)}, {int((~clear).sum())} near-tie rows, "
+        f"max weight rel err {rel.max():.2e}")
+    assert rel.max() <= 2e-4
+    # the graph is a valid operator input, and the operator accepts it
+    op = gl.Operator(torch.from_numpy(rp).to(DEV), torch.from_numpy(col).to(DEV),
+                     torch.from_numpy(w).to(DEV), store_w="f32")
+    assert op.info()["nnz"] == len(col)
+
+
+def test_knn_graph_duplicates_and_errors():
+    # four coincident points and one far away: zero scales take the floor,
+    # coincident pairs get weight 1, the far point is isolated -> rejected
+    x = np.array([[0.0], [0.0], [0.0], [0.0], [1e3]], dtype=np.float64)
+    idx, d2 = knn_oracle.knn(x, 2)
+    with pytest.raises(gl.GLError):
+        _graph_gpu(idx.astype(np.int32), d2.astype(np.float32), 1)
+    x = np.array([[0.0], [0.0], [0.0], [0.0], [1.0], [1.0], [1.0]], dtype=np.float64)
+    idx, d2 = knn_oracle.knn(x, 3)
+    rp, col, w = _graph_gpu(idx.astype(np.int32), d2.astype(np.float32), 1)
+    orp, ocol, ow = knn_oracle.graph_from_knn(7, idx, d2, 1)
+    assert rp.tolist() == orp.tolist() and col.tolist() == ocol.tolist()
+    assert np.array_equal(w, ow)
+    good_i = np.array([[1], [0], [1]], dtype=np.int32)
+    good_d = np.ones((3, 1), dtype=np.float32)
+    for bad_i, bad_d in [(np.array([[0], [0], [1]], np.int32), good_d),     # self
+                         (np.array([[1], [3], [1]], np.int32), good_d),     # out of range
+                         (good_i, np.array([[1], [-1], [1]], np.float32)),  # negative
+                         (good_i, np.array([[1], [np.nan], [1]], np.float32))]:
+        with pytest.raises(gl.GLError):
+            _graph_gpu(bad_i, bad_d, 1)

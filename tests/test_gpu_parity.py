@@ -284,7 +284,7 @@ def test_solve_config3_full(store):
     _check_solve(p, *store)
 
 
-@pytest.mark.parametrize("layout", ["tile", "direct"])
+@pytest.mark.parametrize("layout", ["tile", "direct", "grid"])
 @pytest.mark.parametrize("store", [("bf16", "f16"), ("f32", "f32")])
 def test_solve_config4_small(store, layout):
     p = problem(4, small=True)
@@ -292,11 +292,12 @@ def test_solve_config4_small(store, layout):
     _check_solve(p, *store, lam, layout=layout, expect_layout=layout)
 
 
+@pytest.mark.parametrize("layout", ["auto", "grid"])
 @pytest.mark.parametrize("store", [("bf16", "f16"), ("f32", "f32")])
-def test_solve_config4_full(store):
+def test_solve_config4_full(store, layout):
     p = problem(4)
     _, lam = oracle_lambda(p)
-    _check_solve(p, *store, lam, expect_layout="tile")
+    _check_solve(p, *store, lam, layout=layout, expect_layout="tile" if layout == "auto" else "grid")
 
 
 def test_solve_config2_full_direct_natural_order():
