@@ -124,8 +124,8 @@ typedef enum gl_laplacian { GL_LAP_NORMALIZED = 0, GL_LAP_UNNORMALIZED = 1 } gl_
  *            chunks of 8, and stages each 64 x 8 pixel tile's 15 x 15 window
  *            halo of the field in LDS; it takes no `order` and is built on
  *            the host (the CSR pattern is copied back once).  One call with K
- *            columns needs K * 78 * 22 * (4 or 8 bytes) <= 65536 of LDS,
- *            checked per call.
+ *            columns needs K * 78 * 22 * (field element size: 2, 4 or 8
+ *            bytes) <= 65536 of LDS, checked per call.
  * Every degree d_i = sum_j w_ij must be > 0. */
 typedef struct gl_graph {
     int64_t n;

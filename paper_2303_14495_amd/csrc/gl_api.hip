@@ -131,7 +131,7 @@ bool pair_ok(gl_dtype w, gl_dtype u) {
 // The window layout stages K columns of its tile's halo in LDS.
 gl_status window_fits(const gl_operator* op, int K, gl_dtype u) {
     if (op->layout == gl::LAYOUT_GRID) {
-        const size_t need = (size_t)K * gl::kGridCells * (u == GL_F64 ? 8 : 4);
+        const size_t need = (size_t)K * gl::kGridCells * (u == GL_F64 ? 8 : u == GL_F32 ? 4 : 2);
         if (need > gl::kGridLdsMax)
             return fail(GL_E_INVALID_ARG, "grid operator: K = " + std::to_string(K) + " columns need " +
                                               std::to_string(need) + " B of LDS per block (limit " +

@@ -120,6 +120,19 @@ __device__ __forceinline__ void load_row(const T* __restrict__ p, A (&out)[K]) {
     for (int k = 0; k < K; ++k) out[k] = cvt<A>(vals[k]);
 }
 
+// K values of one row as stored, without conversion.
+template <int K, typename T>
+__device__ __forceinline__ void load_raw(const T* __restrict__ p, T (&out)[K]) {
+    constexpr int RB = K * (int)sizeof(T);
+    constexpr int CB = (RB % 16 == 0) ? 16 : (RB % 8 == 0) ? 8 : (RB % 4 == 0) ? 4 : 2;
+    typedef typename chunk_t<CB>::type C;
+    C buf[RB / CB];
+    const C* src = reinterpret_cast<const C*>(p);
+#pragma unroll
+    for (int c = 0; c < RB / CB; ++c) buf[c] = src[c];
+    __builtin_memcpy(out, buf, RB);
+}
+
 // Fused multiply-add with one rounding, written out where the result must not
 // depend on how the compiler contracts an expression in a given kernel.
 __device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

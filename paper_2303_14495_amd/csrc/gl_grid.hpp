@@ -72,12 +72,24 @@ __device__ __forceinline__ void block_stats_lanes(A (&e)[K], A (&r)[K], A* __res
     }
 }
 
+// Type of the staged field: 16-bit fields are staged as stored (half the LDS
+// bytes and traffic of float, converted on read); wider ones in the
+// accumulator type.
+template <typename TU, typename A> struct grid_lds { typedef A type; };
+template <typename A> struct grid_lds<bf16, A> { typedef bf16 type; };
+template <typename A> struct grid_lds<f16, A> { typedef f16 type; };
+
+template <typename TU, typename A>
+constexpr size_t grid_lds_bytes(int K) { return (size_t)K * kGridCells * sizeof(typename grid_lds<TU, A>::type); }
+
 // Z = W V for the lane's pixel; the pixel's own V row comes from the staged tile.
 //   prefetch(ok, p): issue the loads of the pixel's own data
 //   finish(ok, p, z, v): consume the product
 template <int K, typename TW, typename TU, typename A, typename Pre, typename Fin>
-__device__ __forceinline__ void grid_products(const GridOp& op, const TU* __restrict__ V, int64_t b, A* hv,
+__device__ __forceinline__ void grid_products(const GridOp& op, const TU* __restrict__ V, int64_t b, void* lds,
                                               Pre&& prefetch, Fin&& finish) {
+    typedef typename grid_lds<TU, A>::type L;
+    L* hv = static_cast<L*>(lds);
     constexpr int NV = kGridChunk * (int)sizeof(TW) / 16;  // 16-byte vectors per chunk
     const int ty = (int)(b / op.tiles_x), tx = (int)(b - (int64_t)ty * op.tiles_x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
@@ -93,7 +105,7 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     // cells outside the image afterwards
     const int gx0 = tx * kGridTX - kGridR, gy0 = ty * kGridTY - kGridR;
     for (int c0 = 0; c0 < kGridCells; c0 += 4 * kGridThreads) {
-        A vals[4][K];
+        L vals[4][K];
         bool in[4];
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
@@ -104,14 +116,19 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
             in[u] = gy >= 0 && gy < op.height && gx >= 0 && gx < op.width;
             const int gyc = gy < 0 ? 0 : (gy >= op.height ? op.height - 1 : gy);
             const int gxc = gx < 0 ? 0 : (gx >= op.width ? op.width - 1 : gx);
-            load_row<K>(V + ((int64_t)gyc * op.width + gxc) * K, vals[u]);
+            const TU* src = V + ((int64_t)gyc * op.width + gxc) * K;
+            if constexpr (sizeof(L) == sizeof(TU)) {
+                load_raw<K>(src, vals[u]);
+            } else {
+                load_row<K>(src, vals[u]);
+            }
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const int c = c0 + u * kGridThreads + (int)threadIdx.x;
             if (c < kGridCells) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) hv[c * K + k] = in[u] ? vals[u][k] : (A)0;
+                for (int k = 0; k < K; ++k) hv[c * K + k] = in[u] ? vals[u][k] : store_as<L>::from((A)0);
             }
         }
     }
@@ -153,11 +170,12 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
                     const uint32_t byte = (uint32_t)(ob[u] >> (8 * e)) & 0xffu;
                     const int at = rowbase + (int)(byte >> 4) * kGridS + (int)(byte & 15u);
                     const A w = cvt<A>(we[e]);
-                    A hvv[K];
-                    constexpr int kAl = (K * sizeof(A)) % 16 == 0 ? 16 : (K * sizeof(A)) % 8 == 0 ? 8 : 4;
+                    L hvv[K];
+                    constexpr int kAl = (K * sizeof(L)) % 16 == 0 ? 16 : (K * sizeof(L)) % 8 == 0 ? 8
+                                      : (K * sizeof(L)) % 4 == 0 ? 4 : 2;
                     __builtin_memcpy(hvv, __builtin_assume_aligned(&hv[at * K], kAl), sizeof(hvv));
 #pragma unroll
-                    for (int k = 0; k < K; ++k) z[k] += w * hvv[k];
+                    for (int k = 0; k < K; ++k) z[k] += w * cvt<A>(hvv[k]);
                 }
             }
         }
@@ -165,7 +183,7 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     const int center = (wave + kGridR) * kGridS + lane + kGridR;
     A vc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) vc[k] = hv[center * K + k];
+    for (int k = 0; k < K; ++k) vc[k] = cvt<A>(hv[center * K + k]);
     finish(ok, p, z, vc);
 }
 
@@ -187,7 +205,7 @@ template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<TU, typename acc_of<TU>::type> a) {
     typedef typename acc_of<TU>::type A;
     extern __shared__ unsigned char smem_raw[];
-    A* hv = reinterpret_cast<A*>(smem_raw);
+    void* hv = smem_raw;
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     int32_t lab = -1;
     A dl = (A)1;
@@ -237,7 +255,7 @@ template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(kGridThreads) void grid_laplacian_kernel(GridLapArgs<TU> a) {
     typedef typename acc_of<TU>::type A;
     extern __shared__ unsigned char smem_raw[];
-    A* hv = reinterpret_cast<A*>(smem_raw);
+    void* hv = smem_raw;
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     A dl = (A)1;
     auto prefetch = [&](bool ok, int64_t p) {
@@ -265,7 +283,7 @@ struct GridPowerArgs {
 template <typename TW>
 __global__ __launch_bounds__(kGridThreads) void grid_power_kernel(GridPowerArgs a) {
     extern __shared__ unsigned char smem_raw[];
-    float* hv = reinterpret_cast<float*>(smem_raw);
+    void* hv = smem_raw;
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const float s = a.mode == 0 ? *a.scale : 1.0f;
     float dl = 1.f, p0 = 0.f, p1 = 0.f;

@@ -203,7 +203,7 @@ static hipError_t grid_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
     a.energy = L.energy;
     a.k = make_sweep_args<TW, TU, int32_t>(L).k;
     const dim3 grid((unsigned)L.r.grid), block(kGridThreads);
-    const size_t lds = (size_t)K * kGridCells * sizeof(A);
+    const size_t lds = grid_lds_bytes<TU, A>(K);
     switch (K) {
 #define GL_CASE(KK)                                                                       \
     case KK:                                                                              \
@@ -226,7 +226,7 @@ static hipError_t grid_laplacian_k(int K, const RowLaunch& r, const void* x, voi
     a.y = static_cast<TU*>(y);
     a.dd = static_cast<const A*>(r.dd);
     const dim3 grid((unsigned)r.grid), block(kGridThreads);
-    const size_t lds = (size_t)K * kGridCells * sizeof(A);
+    const size_t lds = grid_lds_bytes<TU, A>(K);
     switch (K) {
 #define GL_CASE(KK)                                                                        \
     case KK:                                                                               \
