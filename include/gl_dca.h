@@ -465,12 +465,27 @@ gl_status gl_server_destroy(gl_server *srv);
  *            by ascending squared distance, ties to the lower index
  *   d2_out   device f32 [n x k] or NULL: those squared distances, computed
  *            as sum_c (x_ic - x_jc)^2 in f32 in coordinate order
- * 1 <= d <= 64, 1 <= k <= 32, k < n < 2^31.  A point with a non-finite
- * coordinate is never chosen as a neighbour; a list that cannot be filled
- * ends with index -1 and distance +inf.  Asynchronous on `stream`.
- * Errors: GL_E_INVALID_ARG, GL_E_HIP. */
+ * 1 <= d <= 4096, 1 <= k <= 32, k < n < 2^31.
+ * d <= 64: one register-resident scan per query, asynchronous on `stream`; a
+ * point with a non-finite coordinate is never chosen as a neighbour, and a
+ * list that cannot be filled ends with index -1 and distance +inf.
+ * d > 64 (wide features, e.g. 784 pixels): the same result, found through
+ * the matrix cores: <x_i, x_j> of the centred points rounded to f16 (scaled
+ * by a power of two) by a rocBLAS GEMM with f32 accumulation, in chunks of at
+ * most 2 GiB of f32 products; per query the 64 best approximate distances
+ * become candidates whose exact distances are recomputed, and a
+ * certificate from the rounding-error bound proves that no other point can
+ * enter or tie the k best; queries without it are rescanned exactly
+ * (gl_knn_fallback_rows).  Non-finite coordinates are rejected
+ * (GL_E_INVALID_ARG).  Allocates about n (2 d + 8) bytes plus the chunk as
+ * stream-ordered temporaries and synchronises `stream`.
+ * Errors: GL_E_INVALID_ARG, GL_E_NOMEM, GL_E_HIP. */
 gl_status gl_knn(const float *x, int64_t n, int32_t d, int32_t k, int32_t *idx_out,
                  float *d2_out, void *stream);
+
+/* Host: queries of the calling thread's last gl_knn call with d > 64 that
+ * needed the exact rescan (0 after a call with d <= 64, -1 after an error). */
+int64_t gl_knn_fallback_rows(void);
 
 /* Message of the last non-OK status returned to the calling thread. */
 const char *gl_last_error(void);

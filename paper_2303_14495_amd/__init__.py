@@ -10,6 +10,7 @@ from .gl import (  # noqa: F401
     Server,
     assign_labels,
     knn,
+    knn_fallback_rows,
     knn_graph,
     load_library,
     split_stats,

@@ -16,7 +16,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgl_dca.so")
-SOURCES = ["gl_api.hip", "gl_layout.hip", "gl_server.hip", "gl_knn.hip", "gl_eigen.hip", "gl_window.hip", "gl_graph.hip", "gl_unit_f64.hip", "gl_unit_f32.hip",
+SOURCES = ["gl_api.hip", "gl_layout.hip", "gl_server.hip", "gl_knn.hip", "gl_eigen.hip", "gl_window.hip", "gl_graph.hip", "gl_knn_wide.hip", "gl_unit_f64.hip", "gl_unit_f32.hip",
            "gl_unit_bf16.hip", "gl_unit_f16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
@@ -54,7 +54,8 @@ def build(verbose: bool = False, incremental: bool = False) -> str:
     with ThreadPoolExecutor(max_workers=jobs) as ex:
         objs = list(ex.map(lambda f: _compile(f, incremental), SOURCES))
     tmp = LIB + ".tmp"
-    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
+    cmd = [HIPCC, f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs,
+           "-L/opt/rocm/lib", "-lrocblas", "-Wl,-rpath,/opt/rocm/lib"]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stderr}")

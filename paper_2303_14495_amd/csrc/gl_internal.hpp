@@ -101,6 +101,11 @@ RowLaunch operator_rows(const gl_operator* op);
 hipError_t launch_window_power(const gl_operator* op, const float* x, float* y, int mode, const float* scale,
                                float* partials, hipStream_t s);
 
+// gl_knn for 64 < d <= 4096 (arguments checked by the caller); *fallback_rows
+// receives the number of rows recomputed by the exact scan.
+gl_status knn_wide(const float* x, int64_t n, int32_t d, int32_t k, int32_t* idx_out, float* d2_out,
+                   hipStream_t s, int64_t* fallback_rows);
+
 // LDS bytes one window-layout block needs for K columns of accumulator size acc.
 size_t window_lds_bytes(const gl_operator* op, int K, size_t acc);
 

@@ -129,14 +129,20 @@ static hipError_t knn_launch(const float* x, int64_t n, int32_t d, int32_t k, in
 
 }  // namespace gl
 
+namespace {
+thread_local int64_t g_knn_fallback = 0;
+}
+
+extern "C" int64_t gl_knn_fallback_rows(void) { return g_knn_fallback; }
+
 extern "C" gl_status gl_knn(const float* x, int64_t n, int32_t d, int32_t k, int32_t* idx_out, float* d2_out,
                             void* stream) {
     if (!x || !idx_out) {
         gl::set_last_error("x and idx_out must not be NULL");
         return GL_E_INVALID_ARG;
     }
-    if (d < 1 || d > 64) {
-        gl::set_last_error("d must lie in [1, 64]");
+    if (d < 1 || d > 4096) {
+        gl::set_last_error("d must lie in [1, 4096]");
         return GL_E_INVALID_ARG;
     }
     if (k < 1 || k > 32) {
@@ -147,6 +153,13 @@ extern "C" gl_status gl_knn(const float* x, int64_t n, int32_t d, int32_t k, int
         gl::set_last_error("need k < n < 2^31");
         return GL_E_INVALID_ARG;
     }
+    if (d > 64) {
+        int64_t fb = 0;
+        const gl_status st = gl::knn_wide(x, n, d, k, idx_out, d2_out, (hipStream_t)stream, &fb);
+        g_knn_fallback = st == GL_OK ? fb : -1;
+        return st;
+    }
+    g_knn_fallback = 0;
     const hipError_t e = gl::knn_launch(x, n, d, k, idx_out, d2_out, (hipStream_t)stream);
     if (e != hipSuccess) {
         gl::set_last_error(std::string("knn launch: ") + hipGetErrorString(e));

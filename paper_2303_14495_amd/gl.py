@@ -92,6 +92,7 @@ SIGNATURES = {
     "gl_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "gl_window_operator_create": (ctypes.c_int, [_P, _I32, _P, _P]),
     "gl_knn_graph": (ctypes.c_int, [_I64, _I32, _P, _P, _I32, _P, _P, _P, _I64, _P, _P]),
+    "gl_knn_fallback_rows": (ctypes.c_int64, []),
     "gl_operator_destroy": (ctypes.c_int, [_P]),
     "gl_operator_info": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
     "gl_operator_layout": (ctypes.c_int, [_P, _P, _P, _P, _P, _P]),
@@ -391,6 +392,12 @@ def assign_labels(U: torch.Tensor, stream=None) -> torch.Tensor:
                                            DTYPES[DTYPE_OF_TORCH[U2.dtype]], _ptr(U2), _ptr(out),
                                            _stream_handle(stream)))
     return out
+
+
+def knn_fallback_rows() -> int:
+    """Queries of this thread's last wide-feature (d > 64) kNN call that needed
+    the exact rescan."""
+    return int(load_library().gl_knn_fallback_rows())
 
 
 def knn(x: torch.Tensor, k: int, with_distances: bool = True, stream=None):

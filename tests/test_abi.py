@@ -87,7 +87,7 @@ def test_null_arguments_rejected():
     assert lib.gl_knn(None, 100, 3, 5, None, None, None) == 1
 
 
-@pytest.mark.parametrize("n,d,k", [(100, 0, 5), (100, 65, 5), (100, 3, 0), (100, 3, 33), (5, 3, 5)])
+@pytest.mark.parametrize("n,d,k", [(100, 0, 5), (100, 4097, 5), (100, 3, 0), (100, 3, 33), (5, 3, 5)])
 def test_knn_sizes_rejected(n, d, k):
     # size checks come before any device access (dummy non-NULL pointers)
     lib = gl.load_library()

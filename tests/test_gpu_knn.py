@@ -105,7 +105,7 @@ def test_knn_rejects_bad_sizes():
         with pytest.raises(gl.GLError):
             gl.knn(x, k)
     with pytest.raises(gl.GLError):
-        gl.knn(torch.zeros((10, 65), device=DEV), 3)
+        gl.knn(torch.zeros((10, 4097), device=DEV), 3)
 
 
 # ---------------------------------------------------------------------------
@@ -183,3 +183,63 @@ def test_knn_graph_duplicates_and_errors():
                          (good_i, np.array([[1], [np.nan], [1]], np.float32))]:
         with pytest.raises(gl.GLError):
             _graph_gpu(bad_i, bad_d, 1)
+
+
+# ---------------------------------------------------------------------------
+# wide features (d > 64): f16 Gram matrix on the matrix cores, exact refine,
+# certificate, exact rescan of uncertified rows
+# ---------------------------------------------------------------------------
+
+def _exact_f32(x, rows, idx):
+    """Distances as the kernels form them: f32 fused multiply-adds in
+    coordinate order (t^2 is exact in float64, one rounding per step)."""
+    acc = np.zeros(idx.shape, dtype=np.float32)
+    q = x[np.asarray(rows)][:, None, :]
+    p = x[idx]
+    for c in range(x.shape[1]):
+        t = (q[..., c] - p[..., c]).astype(np.float32)
+        acc = (acc.astype(np.float64) + t.astype(np.float64) ** 2).astype(np.float32)
+    return acc
+
+
+@pytest.mark.parametrize("n,d,k", [(3000, 65, 10), (3000, 100, 1), (2500, 784, 10), (2100, 300, 32)])
+def test_knn_wide_matches_oracle(n, d, k):
+    x = mixture(n, d, seed=d + k)
+    say(f"wide knn n={n} d={d} k={k}")
+    idx, d2 = gl.knn(torch.from_numpy(x).to(DEV), k)
+    fb = gl.knn_fallback_rows()
+    idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
+    frac = check(x, k, idx, d2, np.arange(n))
+    say(f"  clear rows {frac:.4f}, exact rescans {fb}")
+    assert frac > 0.5  # concentrated distances in high dimension: many near-ties
+    assert fb <= n // 20
+    # the distances are the kernels' own f32 sums (up to the emulation's double rounding)
+    ref = _exact_f32(x, np.arange(n), idx)
+    assert np.abs(d2 - ref).max() <= 1e-6 * max(1.0, float(ref.max()))
+
+
+def test_knn_wide_ties_use_the_exact_rescan():
+    """The 96 unit vectors of R^96 are all at squared distance 2 from each
+    other: every candidate ties with points outside the 64 candidates, so
+    those rows lose the certificate and are rescanned exactly; with other
+    integer points (and duplicates) around, the result must equal the float64
+    oracle exactly, ties to the lower index."""
+    rng = np.random.default_rng(12)
+    n, d, k = 1200, 96, 12
+    x = rng.integers(0, 3, (n, d)).astype(np.float32) + 4.0
+    x[:d] = np.eye(d, dtype=np.float32)
+    x[300:360] = x[200:260]  # exact duplicates: distance-0 ties
+    idx, d2 = gl.knn(torch.from_numpy(x).to(DEV), k)
+    fb = gl.knn_fallback_rows()
+    oi, od = knn_oracle.knn(x.astype(np.float64), k)
+    say(f"wide knn ties: exact rescans {fb} of {n}")
+    assert fb >= d
+    assert np.array_equal(idx.cpu().numpy(), oi)
+    assert np.array_equal(d2.cpu().numpy(), od.astype(np.float32))
+
+
+def test_knn_wide_rejects_nonfinite():
+    x = mixture(500, 80, seed=1)
+    x[7, 3] = np.nan
+    with pytest.raises(gl.GLError):
+        gl.knn(torch.from_numpy(x).to(DEV), 5)
