@@ -32,7 +32,7 @@ METRIC = "Laplacian-sweep HBM GB/s + DCA solves/s (FP32 vs BF16); served p50/p99
 DSIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 
 
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "tile_sweep_image2048_k4_traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_sweep_image2048_k4_traffic.json")
 # sources whose change invalidates recorded counter traffic of the sweep kernel
 WINDOW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_sweep_1024_r12_traffic.json")  # + _<weights>
 TRAFFIC_SOURCES = ["gl_tile.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
