@@ -92,6 +92,8 @@ def parse():
     ap.add_argument("--served-rate", type=float, default=0.8,
                     help="arrival rate as a fraction of one-at-a-time f32 capacity")
     ap.add_argument("--served-budget-gib", type=float, default=32.0)
+    ap.add_argument("--served-rates", default="",
+                    help="comma-separated extra arrival rates, as multiples of the f32 capacity")
     ap.add_argument("--served-slots", type=int, default=32)
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 1 GiB device copy (counter calibration)")
@@ -257,7 +259,7 @@ def run_served_stream(reqs, arrivals, budget, slots):
     return lat, makespan, [x["labels"] for x in res], info
 
 
-def served_bench(dev, count, rate_factor, budget_gib, slots):
+def served_bench(dev, count, rate_factor, budget_gib, slots, extra_rates=()):
     import numpy as np
     log(f"served stream: generating {count} requests")
     t = time.perf_counter()
@@ -301,6 +303,23 @@ def served_bench(dev, count, rate_factor, budget_gib, slots):
         f"{out['served_bf16']['p99_ms']:.1f} ms; fp32 p50 "
         f"{out['fp32_one_at_a_time']['p50_ms']:.1f} ms p99 "
         f"{out['fp32_one_at_a_time']['p99_ms']:.1f} ms; agreement {agree:.5f}")
+    # the same stream at other arrival rates (multiples of the f32 capacity)
+    sweep = []
+    for f in extra_rates:
+        r2 = f * cap32
+        arr2 = [r["t"] / r2 for r in reqs]
+        l32, sp32, _ = run_fp32_stream(dev, reqs, arr2)
+        ls, sps, _, inf2 = run_served_stream(reqs, arr2, budget, slots)
+        row = {"rate_factor": f, "arrival_rate_per_s": r2,
+               "served_bf16": {"solves_per_s": count / sps, "p50_ms": pct(ls, 50), "p99_ms": pct(ls, 99)},
+               "fp32_one_at_a_time": {"solves_per_s": count / sp32, "p50_ms": pct(l32, 50),
+                                      "p99_ms": pct(l32, 99)}}
+        sweep.append(row)
+        log(f"  at {f:.2f} x capacity ({r2:.1f} req/s): served p50 {row['served_bf16']['p50_ms']:.1f} ms "
+            f"p99 {row['served_bf16']['p99_ms']:.1f} ms; fp32 p50 {row['fp32_one_at_a_time']['p50_ms']:.1f} ms "
+            f"p99 {row['fp32_one_at_a_time']['p99_ms']:.1f} ms")
+    if sweep:
+        out["rate_sweep"] = sweep
     return out
 
 
@@ -465,8 +484,9 @@ def main():
         print(json.dumps(window_bench(dev, args.steps, args.warmup, args.sweep_reps)), flush=True)
         return
     if args.served_only:
+        rates = [float(v) for v in args.served_rates.split(",") if v]
         print(json.dumps(served_bench(dev, args.served_count, args.served_rate,
-                                      args.served_budget_gib, args.served_slots)), flush=True)
+                                      args.served_budget_gib, args.served_slots, rates)), flush=True)
         return
     log(f"generating workload {args.workload}")
     t = time.perf_counter()
@@ -558,10 +578,18 @@ def main():
             if time.perf_counter() - t0 >= 10.0 or solves >= 20:
                 break
         t_cpu = time.perf_counter() - t0
+        model = ""
+        try:
+            with open("/proc/cpuinfo") as fh:
+                model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
+        except OSError:
+            pass
         cpu = {"value": solves / t_cpu, "unit": "solves/s",
                "cores": c_oracle.num_threads(), "kind": "oracle",
                "sample": (f"{solves} whole solves ({p.outer} DCA steps x {p.sweeps} sweeps + "
-                          f"energies, float64, C+OpenMP) on the full graph, {t_cpu:.1f} s")}
+                          f"energies, float64, C+OpenMP) on the full graph, {t_cpu:.1f} s"),
+               "s_per_sweep": t_cpu / (solves * p.outer * p.sweeps),  # energies included
+               "cpu_model": model, "host_cpus": os.cpu_count()}
 
     log("unsupervised run (second eigenvector start)")
     unsup = unsupervised_bench(dev)
