@@ -41,21 +41,61 @@ struct GridOp {
     int32_t height, width, tiles_x;
 };
 
+// Sum over the 64 lanes of a wavefront in a fixed order, with DPP lane moves
+// (no LDS traffic); the total is valid in lane 63.  Steps: lane ^ 1, lane ^ 2,
+// mirror within 8 lanes, mirror within 16 lanes (every lane then holds its
+// row's sum), rows 1 and 3 add the last lane of rows 0 and 2, rows 2 and 3
+// add lane 31.
+template <int CTRL, int ROWS> __device__ __forceinline__ int dpp_mov(int v) {
+    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);  // 0 in rows outside ROWS
+}
+
+template <int CTRL, int ROWS, typename A> __device__ __forceinline__ A dpp_add(A x) {
+    if constexpr (sizeof(A) == 4) {
+        return x + __builtin_bit_cast(A, dpp_mov<CTRL, ROWS>(__builtin_bit_cast(int, x)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = (uint32_t)dpp_mov<CTRL, ROWS>((int)(uint32_t)u);
+        const uint32_t hi = (uint32_t)dpp_mov<CTRL, ROWS>((int)(uint32_t)(u >> 32));
+        return x + __builtin_bit_cast(A, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+template <typename A> __device__ __forceinline__ A wave_sum63(A x) {
+    x = dpp_add<0xb1, 0xf>(x);   // quad_perm [1, 0, 3, 2]
+    x = dpp_add<0x4e, 0xf>(x);   // quad_perm [2, 3, 0, 1]
+    x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
+    x = dpp_add<0x140, 0xf>(x);  // row_mirror
+    x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
+    return dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
+}
+
+// Largest value of a non-negative int over the wavefront (same steps), as a
+// wave-uniform value.
+__device__ __forceinline__ int wave_max_nonneg(int x) {
+    x = max(x, dpp_mov<0xb1, 0xf>(x));
+    x = max(x, dpp_mov<0x4e, 0xf>(x));
+    x = max(x, dpp_mov<0x141, 0xf>(x));
+    x = max(x, dpp_mov<0x140, 0xf>(x));
+    x = max(x, dpp_mov<0x142, 0xa>(x));
+    x = max(x, dpp_mov<0x143, 0xc>(x));
+    return __builtin_amdgcn_readlane(x, 63);
+}
+
 // Fixed-order block reduction of per-lane column statistics for NW wavefronts
-// (as block_stats, every lane holding all K columns).
+// (as block_stats, every lane holding all K columns).  with_e = false: the e
+// statistics are known to be zero and are written as such.
 template <int K, int NW, typename A>
 __device__ __forceinline__ void block_stats_lanes(A (&e)[K], A (&r)[K], A* __restrict__ partials, int64_t nb,
-                                                  int64_t b) {
+                                                  int64_t b, bool with_e = true) {
     __shared__ A sh[NW][2][K];
-    for (int off = 1; off < 64; off <<= 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) {
-            e[k] += __shfl_xor(e[k], off, 64);
-            r[k] += __shfl_xor(r[k], off, 64);
-        }
+    for (int k = 0; k < K; ++k) {
+        r[k] = wave_sum63(r[k]);
+        e[k] = with_e ? wave_sum63(e[k]) : (A)0;
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    if (lane == 0) {
+    if (lane == 63) {
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             sh[wave][0][k] = e[k];
@@ -82,6 +122,46 @@ template <typename A> struct grid_lds<f16, A> { typedef f16 type; };
 template <typename TU, typename A>
 constexpr size_t grid_lds_bytes(int K) { return (size_t)K * kGridCells * sizeof(typename grid_lds<TU, A>::type); }
 
+// LDS byte offsets, from the start of the staged tile, of the 8 entries of a
+// chunk (offset bytes ob) for a lane whose window corner is at byte rowb.
+// Entry byte x = (dy + 7) * 16 + (dx + 7) sits (dy + 7) * S + (dx + 7) =
+// x + (S - 16) * (x >> 4) cells from the corner.  Two entries are decoded at
+// once in the 16-bit halves of a register (packed integer arithmetic); this
+// needs every offset below 2^16, i.e. a staged tile of at most 64 KB, which
+// is the LDS limit the host enforces.  Offsets come out in entry order.
+template <int CB>
+__device__ __forceinline__ void grid_chunk_offsets(uint64_t ob, uint32_t rowb, uint32_t (&at)[kGridChunk]) {
+    typedef unsigned short u16x2 __attribute__((ext_vector_type(2)));
+    static_assert((size_t)kGridCells * CB <= 65536, "16-bit LDS offsets");
+    // the multipliers are hidden from the optimizer so that each pair costs two
+    // multiply-adds rather than shifts and adds
+    uint32_t cbw = (uint32_t)CB * 0x10001u, rbw = (uint32_t)(CB * (kGridS - 16)) * 0x10001u;
+    asm("" : "+s"(cbw));
+    asm("" : "+s"(rbw));
+    u16x2 cb, cbrow;
+    __builtin_memcpy(&cb, &cbw, 4);
+    __builtin_memcpy(&cbrow, &rbw, 4);
+    const u16x2 base = {(unsigned short)rowb, (unsigned short)rowb};
+    const u16x2 four = {4, 4};
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+        const uint32_t wd = (uint32_t)(ob >> (32 * h));
+#pragma unroll
+        for (int q = 0; q < 2; ++q) {
+            // bytes q and q + 2 of the word, zero-extended into the two halves:
+            // entries 4h + q (low half) and 4h + q + 2 (high half)
+            const uint32_t pr = __builtin_amdgcn_perm(wd, wd, q == 0 ? 0x0c020c00u : 0x0c030c01u);
+            u16x2 x;
+            __builtin_memcpy(&x, &pr, 4);
+            const u16x2 a = x * cb + ((x >> four) * cbrow + base);
+            uint32_t av;
+            __builtin_memcpy(&av, &a, 4);
+            at[4 * h + q] = av & 0xffffu;
+            at[4 * h + q + 2] = av >> 16;
+        }
+    }
+}
+
 // Z = W V for the lane's pixel; the pixel's own V row comes from the staged tile.
 //   prefetch(ok, p): issue the loads of the pixel's own data
 //   finish(ok, p, z, v): consume the product
@@ -91,7 +171,8 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     typedef typename grid_lds<TU, A>::type L;
     L* hv = static_cast<L*>(lds);
     constexpr int NV = kGridChunk * (int)sizeof(TW) / 16;  // 16-byte vectors per chunk
-    const int ty = (int)(b / op.tiles_x), tx = (int)(b - (int64_t)ty * op.tiles_x);
+    const int bi = (int)b;  // tiles < 2^31: 2^31 tiles of 512 pixels would not fit in memory
+    const int ty = bi / op.tiles_x, tx = bi - ty * op.tiles_x;
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
     const int x = tx * kGridTX + lane, y = ty * kGridTY + wave;
     const bool ok = x < op.width && y < op.height;
@@ -99,6 +180,43 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     const int cnt = ok ? (int)op.cnt[p] : 0;
     const int64_t wb = y < op.height ? op.wbase[(int64_t)y * op.tiles_x + tx] : 0;
     prefetch(ok, p);
+
+    const int maxc = wave_max_nonneg(cnt);
+    const uint64_t below = (1ull << lane) - 1ull;
+    const int rowbase = wave * kGridS + lane;  // staged cell of window offset (-7, -7)
+    constexpr int kCB = K * (int)sizeof(L);    // bytes per staged cell
+    // tiles beyond 64 KB are rejected by the host; their instantiations keep
+    // the 32-bit decode so that they still compile
+    constexpr bool kPacked = (size_t)kGridCells * kCB <= 65536;
+    const uint32_t rowb = (uint32_t)rowbase * kCB;
+    const unsigned char* hb = static_cast<const unsigned char*>(lds);
+    const u32x4* wv4 = static_cast<const u32x4*>(op.w);
+    int64_t next = wb;
+    A z[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = (A)0;
+    // chunks stream in groups of U per lane; the loads of the next group are
+    // issued before the current one is consumed (the first group's before the
+    // tile is staged), so each lane keeps U chunks in flight
+    constexpr int U = 2;
+    uint64_t ob[U], obn[U];
+    u32x4 wq[U][NV], wqn[U][NV];
+    auto fetch = [&](int c) {
+#pragma unroll
+        for (int u = 0; u < U; ++u) {
+            const bool act = c + u < cnt;
+            const uint64_t m = __ballot(act);
+            const int64_t id = next + __popcll(m & below);
+            next += __popcll(m);
+            if (act) {
+                // streamed once per sweep: keep the staged V halos of other tiles in L2
+                obn[u] = __builtin_nontemporal_load(op.offs + id);
+#pragma unroll
+                for (int v = 0; v < NV; ++v) wqn[u][v] = __builtin_nontemporal_load(wv4 + id * NV + v);
+            }
+        }
+    };
+    fetch(0);
 
     // stage V over the tile and its halo: every lane loads its 4 cells from
     // clamped (always valid) addresses, all in flight at once, and zeroes the
@@ -134,46 +252,35 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     }
     __syncthreads();
 
-    int maxc = cnt;
-    for (int off = 32; off > 0; off >>= 1) maxc = max(maxc, __shfl_xor(maxc, off, 64));
-    const uint64_t below = (1ull << lane) - 1ull;
-    const int rowbase = wave * kGridS + lane;  // staged cell of window offset (-7, -7)
-    const u32x4* wv4 = static_cast<const u32x4*>(op.w);
-    int64_t next = wb;
-    A z[K];
-#pragma unroll
-    for (int k = 0; k < K; ++k) z[k] = (A)0;
-    constexpr int U = 2;  // chunks in flight per lane
     for (int c = 0; c < maxc; c += U) {
-        uint64_t ob[U];
-        u32x4 wq[U][NV];
 #pragma unroll
         for (int u = 0; u < U; ++u) {
-            const bool act = c + u < cnt;
-            const uint64_t m = __ballot(act);
-            const int64_t id = next + __popcll(m & below);
-            next += __popcll(m);
-            if (act) {
-                // streamed once per sweep: keep the staged V halos of other tiles in L2
-                ob[u] = __builtin_nontemporal_load(op.offs + id);
+            ob[u] = obn[u];
 #pragma unroll
-                for (int v = 0; v < NV; ++v) wq[u][v] = __builtin_nontemporal_load(wv4 + id * NV + v);
-            }
+            for (int v = 0; v < NV; ++v) wq[u][v] = wqn[u][v];
         }
+        if (c + U < maxc) fetch(c + U);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (c + u < cnt) {
                 TW we[kGridChunk];
                 __builtin_memcpy(we, &wq[u][0], sizeof(we));
+                uint32_t at[kGridChunk];
+                if constexpr (kPacked) {
+                    grid_chunk_offsets<kCB>(ob[u], rowb, at);
+                } else {
+#pragma unroll
+                    for (int e = 0; e < kGridChunk; ++e) {
+                        const uint32_t byte = (uint32_t)(ob[u] >> (8 * e)) & 0xffu;
+                        at[e] = (uint32_t)(rowbase + (int)(byte >> 4) * kGridS + (int)(byte & 15u)) * kCB;
+                    }
+                }
 #pragma unroll
                 for (int e = 0; e < kGridChunk; ++e) {
-                    const uint32_t byte = (uint32_t)(ob[u] >> (8 * e)) & 0xffu;
-                    const int at = rowbase + (int)(byte >> 4) * kGridS + (int)(byte & 15u);
                     const A w = cvt<A>(we[e]);
                     L hvv[K];
-                    constexpr int kAl = (K * sizeof(L)) % 16 == 0 ? 16 : (K * sizeof(L)) % 8 == 0 ? 8
-                                      : (K * sizeof(L)) % 4 == 0 ? 4 : 2;
-                    __builtin_memcpy(hvv, __builtin_assume_aligned(&hv[at * K], kAl), sizeof(hvv));
+                    constexpr int kAl = kCB % 16 == 0 ? 16 : kCB % 8 == 0 ? 8 : kCB % 4 == 0 ? 4 : 2;
+                    __builtin_memcpy(hvv, __builtin_assume_aligned(hb + at[e], kAl), sizeof(hvv));
 #pragma unroll
                     for (int k = 0; k < K; ++k) z[k] += w * cvt<A>(hvv[k]);
                 }
@@ -240,7 +347,7 @@ __global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<
         }
     };
     grid_products<K, TW, TU, A>(a.op, a.vin, b, hv, prefetch, finish);
-    if (a.partials) block_stats_lanes<K, kGridTY>(e_acc, r_acc, a.partials, (int64_t)gridDim.x, b);
+    if (a.partials) block_stats_lanes<K, kGridTY>(e_acc, r_acc, a.partials, (int64_t)gridDim.x, b, a.energy != 0);
 }
 
 // Y = X - What X (L_s X) or D X - W X (L X) on the grid layout
