@@ -125,7 +125,9 @@ typedef enum gl_laplacian { GL_LAP_NORMALIZED = 0, GL_LAP_UNNORMALIZED = 1 } gl_
  *            halo of the field in LDS; it takes no `order` and is built on
  *            the host (the CSR pattern is copied back once).  One call with K
  *            columns needs K * 78 * 22 * (field element size: 2, 4 or 8
- *            bytes) <= 65536 of LDS, checked per call.
+ *            bytes) <= 65536 of LDS and 22 * grid_width * K * (element
+ *            size) < 2^32 bytes, both checked per call (GL_E_INVALID_ARG);
+ *            grid_width < 2^24.
  * Every degree d_i = sum_j w_ij must be > 0. */
 typedef struct gl_graph {
     int64_t n;

@@ -136,6 +136,11 @@ gl_status window_fits(const gl_operator* op, int K, gl_dtype u) {
             return fail(GL_E_INVALID_ARG, "grid operator: K = " + std::to_string(K) + " columns need " +
                                               std::to_string(need) + " B of LDS per block (limit " +
                                               std::to_string(gl::kGridLdsMax) + "); use fewer columns per call");
+        // the staging loads address a block's halo rows with 32-bit byte offsets
+        const uint64_t rows = (uint64_t)gl::kGridHY * (uint64_t)op->wwidth * K * (u == GL_F64 ? 8 : u == GL_F32 ? 4 : 2);
+        if (rows >= (1ull << 32))
+            return fail(GL_E_INVALID_ARG, "grid operator: " + std::to_string(gl::kGridHY) + " image rows of " +
+                                              std::to_string(K) + " columns exceed 4 GiB; use fewer columns per call");
         return GL_OK;
     }
     if (op->layout != gl::LAYOUT_WINDOW) return GL_OK;
@@ -426,6 +431,8 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     if (grid_req) {
         if (g->grid_height < 1 || g->grid_width < 1 || (int64_t)g->grid_height * g->grid_width != g->n)
             return fail(GL_E_INVALID_ARG, "the grid layout needs grid_height * grid_width == n");
+        if (g->grid_width >= (1 << 24))
+            return fail(GL_E_INVALID_ARG, "the grid layout needs grid_width < 2^24");
         if (g->order) return fail(GL_E_INVALID_ARG, "the grid layout takes no order");
     }
     if (g->laplacian != GL_LAP_NORMALIZED && g->laplacian != GL_LAP_UNNORMALIZED)

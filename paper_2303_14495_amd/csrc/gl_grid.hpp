@@ -218,10 +218,14 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     };
     fetch(0);
 
-    // stage V over the tile and its halo: every lane loads its 4 cells from
-    // clamped (always valid) addresses, all in flight at once, and zeroes the
-    // cells outside the image afterwards
+    // stage V over the tile and its halo: every lane issues the loads of its 4
+    // cells at once and zeroes the cells outside the image afterwards.  Loads
+    // use 32-bit byte offsets from the first image row of the halo (the host
+    // keeps 22 rows of V below 2^32 bytes); a cell outside the image loads
+    // that row's first pixel, a valid address.
     const int gx0 = tx * kGridTX - kGridR, gy0 = ty * kGridTY - kGridR;
+    const int gyb = gy0 < 0 ? 0 : gy0;
+    const unsigned char* vb = reinterpret_cast<const unsigned char*>(V + (int64_t)gyb * op.width * K);
     for (int c0 = 0; c0 < kGridCells; c0 += 4 * kGridThreads) {
         L vals[4][K];
         bool in[4];
@@ -231,10 +235,10 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
             const int cc = c < kGridCells ? c : kGridCells - 1;
             const int hy = cc / kGridS, hx = cc - hy * kGridS;
             const int gy = gy0 + hy, gx = gx0 + hx;
-            in[u] = gy >= 0 && gy < op.height && gx >= 0 && gx < op.width;
-            const int gyc = gy < 0 ? 0 : (gy >= op.height ? op.height - 1 : gy);
-            const int gxc = gx < 0 ? 0 : (gx >= op.width ? op.width - 1 : gx);
-            const TU* src = V + ((int64_t)gyc * op.width + gxc) * K;
+            in[u] = (unsigned)gy < (unsigned)op.height && (unsigned)gx < (unsigned)op.width;
+            // row distance <= 21 and width < 2^24 (host checks): 24-bit multiply
+            const uint32_t cell = in[u] ? __umul24((uint32_t)(gy - gyb), (uint32_t)op.width) + (uint32_t)gx : 0u;
+            const TU* src = reinterpret_cast<const TU*>(vb + cell * (uint32_t)(K * sizeof(TU)));
             if constexpr (sizeof(L) == sizeof(TU)) {
                 load_raw<K>(src, vals[u]);
             } else {
@@ -245,8 +249,17 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
         for (int u = 0; u < 4; ++u) {
             const int c = c0 + u * kGridThreads + (int)threadIdx.x;
             if (c < kGridCells) {
+                if constexpr ((K * sizeof(L)) % 4 == 0) {
+                    // select whole words: all-zero bits are +0 in every field type
+                    uint32_t wv[K * sizeof(L) / 4];
+                    __builtin_memcpy(wv, vals[u], sizeof(wv));
 #pragma unroll
-                for (int k = 0; k < K; ++k) hv[c * K + k] = in[u] ? vals[u][k] : store_as<L>::from((A)0);
+                    for (int i = 0; i < (int)(K * sizeof(L) / 4); ++i) wv[i] = in[u] ? wv[i] : 0u;
+                    __builtin_memcpy(&hv[c * K], wv, sizeof(wv));
+                } else {
+#pragma unroll
+                    for (int k = 0; k < K; ++k) hv[c * K + k] = in[u] ? vals[u][k] : store_as<L>::from((A)0);
+                }
             }
         }
     }

@@ -155,3 +155,29 @@ def test_knn_graph_rejects_nulls():
         a = list(args)
         a[pos] = None
         assert lib.gl_knn_graph(*a) == 1
+
+
+@pytest.mark.parametrize("h,w", [(2, 3), (1, 1 << 24), (0, 6)])
+def test_grid_operator_rejects_bad_shapes(h, w):
+    # shape checks come before any device access (dummy non-NULL pointers)
+    lib = gl.load_library()
+    fake = ctypes.c_void_p(4096)
+    n = 6 if (h, w) != (1, 1 << 24) else 1 << 24
+    g = glmod._Graph(n=n, nnz=10, row_ptr=fake.value, col_idx=fake.value, weight=fake.value,
+                     weight_dtype=1, order=None, layout=glmod.LAYOUTS["grid"], laplacian=0,
+                     grid_height=h, grid_width=w if (h, w) != (2, 3) else 4)
+    out = ctypes.c_void_p()
+    assert lib.gl_operator_create(ctypes.byref(g), 1, None, ctypes.byref(out)) == 1
+    assert out.value is None
+    assert b"grid" in lib.gl_last_error()
+
+
+def test_grid_operator_rejects_order():
+    lib = gl.load_library()
+    fake = ctypes.c_void_p(4096)
+    g = glmod._Graph(n=6, nnz=10, row_ptr=fake.value, col_idx=fake.value, weight=fake.value,
+                     weight_dtype=1, order=fake.value, layout=glmod.LAYOUTS["grid"], laplacian=0,
+                     grid_height=2, grid_width=3)
+    out = ctypes.c_void_p()
+    assert lib.gl_operator_create(ctypes.byref(g), 1, None, ctypes.byref(out)) == 1
+    assert b"order" in lib.gl_last_error()
