@@ -133,6 +133,20 @@ __device__ __forceinline__ void load_raw(const T* __restrict__ p, T (&out)[K]) {
     __builtin_memcpy(out, buf, RB);
 }
 
+// K values of one row, stored as they are in as few vector stores as the row's
+// size allows.
+template <int K, typename T>
+__device__ __forceinline__ void store_raw(T* __restrict__ p, const T (&in)[K]) {
+    constexpr int RB = K * (int)sizeof(T);
+    constexpr int CB = (RB % 16 == 0) ? 16 : (RB % 8 == 0) ? 8 : (RB % 4 == 0) ? 4 : 2;
+    typedef typename chunk_t<CB>::type C;
+    C buf[RB / CB];
+    __builtin_memcpy(buf, in, RB);
+    C* dst = reinterpret_cast<C*>(p);
+#pragma unroll
+    for (int c = 0; c < RB / CB; ++c) dst[c] = buf[c];
+}
+
 // Fused multiply-add with one rounding, written out where the result must not
 // depend on how the compiler contracts an expression in a given kernel.
 __device__ __forceinline__ float fma_acc(float a, float b, float c) { return __builtin_fmaf(a, b, c); }

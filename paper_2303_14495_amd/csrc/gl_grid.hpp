@@ -182,7 +182,6 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     prefetch(ok, p);
 
     const int maxc = wave_max_nonneg(cnt);
-    const uint64_t below = (1ull << lane) - 1ull;
     const int rowbase = wave * kGridS + lane;  // staged cell of window offset (-7, -7)
     constexpr int kCB = K * (int)sizeof(L);    // bytes per staged cell
     // tiles beyond 64 KB are rejected by the host; their instantiations keep
@@ -206,7 +205,9 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
         for (int u = 0; u < U; ++u) {
             const bool act = c + u < cnt;
             const uint64_t m = __ballot(act);
-            const int64_t id = next + __popcll(m & below);
+            // rank of this lane among the active ones (mask bits below it)
+            const int64_t id = next + (int64_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             next += __popcll(m);
             if (act) {
                 // streamed once per sweep: keep the staged V halos of other tiles in L2
@@ -342,6 +343,7 @@ __global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<
         if (!ok) return;
         const A lam = lab >= 0 ? (A)1 : (A)0;
         const A ginv = a.dd ? (A)1 / (a.k.ga + a.k.gd * dl + a.k.gl * lam) : (lab >= 0 ? a.k.ginv1 : a.k.ginv0);
+        TU vnew[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const A zk = z[k], u = uu[k], v = vc[k];
@@ -350,7 +352,7 @@ __global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<
             const A lv = a.dd ? dl * v - zk : v - zk;
             const A tv = a.k.eps * lv + (a.k.eta * lam + a.k.c) * v;
             const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
-            if (a.vout) a.vout[p * K + k] = store_as<TU>::from(v + r * ginv);
+            vnew[k] = store_as<TU>::from(v + r * ginv);
             r_acc[k] += r * r;
             if (a.energy) {
                 const A u2m1 = u * u - (A)1, dy = u - y;
@@ -358,6 +360,7 @@ __global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<
                 e_acc[k] += a.k.half_eps * ulu + a.k.quarter_inv_eps * u2m1 * u2m1 + a.k.half_eta * lam * dy * dy;
             }
         }
+        if (a.vout) store_raw<K>(a.vout + p * K, vnew);
     };
     grid_products<K, TW, TU, A>(a.op, a.vin, b, hv, prefetch, finish);
     if (a.partials) block_stats_lanes<K, kGridTY>(e_acc, r_acc, a.partials, (int64_t)gridDim.x, b, a.energy != 0);

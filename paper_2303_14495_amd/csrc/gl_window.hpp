@@ -156,6 +156,7 @@ __global__ __launch_bounds__(256) void window_sweep_kernel(WinSweepArgs<TU, type
         if (!ok) return;
         const A lam = lab >= 0 ? (A)1 : (A)0;
         const A ginv = a.dd ? (A)1 / (a.k.ga + a.k.gd * dl + a.k.gl * lam) : (lab >= 0 ? a.k.ginv1 : a.k.ginv0);
+        TU vnew[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
             const A zk = z[k], u = uu[k], v = vc[k];
@@ -164,7 +165,7 @@ __global__ __launch_bounds__(256) void window_sweep_kernel(WinSweepArgs<TU, type
             const A lv = a.dd ? dl * v - zk : v - zk;
             const A tv = a.k.eps * lv + (a.k.eta * lam + a.k.c) * v;
             const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
-            if (a.vout) a.vout[p * K + k] = store_as<TU>::from(v + r * ginv);
+            vnew[k] = store_as<TU>::from(v + r * ginv);
             r_acc[k] += r * r;
             if (a.energy) {
                 const A u2m1 = u * u - (A)1, dy = u - y;
@@ -172,6 +173,7 @@ __global__ __launch_bounds__(256) void window_sweep_kernel(WinSweepArgs<TU, type
                 e_acc[k] += a.k.half_eps * ulu + a.k.quarter_inv_eps * u2m1 * u2m1 + a.k.half_eta * lam * dy * dy;
             }
         }
+        if (a.vout) store_raw<K>(a.vout + p * K, vnew);
     };
     window_products<K, TW, TU, A>(a.op, a.vin, b, hv, prefetch, finish);
     if (a.partials) block_stats<K, K>(e_acc, r_acc, 1, a.partials, (int64_t)gridDim.x, b);
