@@ -181,6 +181,35 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     const int64_t wb = y < op.height ? op.wbase[(int64_t)y * op.tiles_x + tx] : 0;
     prefetch(ok, p);
 
+    // stage V over the tile and its halo, in two halves around the first
+    // chunk fetch: every lane issues the loads of its 4 cells at once (before
+    // waiting for its chunk count), and writes them to LDS afterwards, cells
+    // outside the image zeroed.  Loads use 32-bit byte offsets from the first
+    // image row of the halo (the host keeps 22 rows of V below 2^32 bytes); a
+    // cell outside the image loads that row's first pixel, a valid address.
+    static_assert(4 * kGridThreads >= kGridCells, "one staging pass");
+    const int gx0 = tx * kGridTX - kGridR, gy0 = ty * kGridTY - kGridR;
+    const int gyb = gy0 < 0 ? 0 : gy0;
+    const unsigned char* vb = reinterpret_cast<const unsigned char*>(V + (int64_t)gyb * op.width * K);
+    L vals[4][K];
+    bool in[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) {
+        const int c = u * kGridThreads + (int)threadIdx.x;
+        const int cc = c < kGridCells ? c : kGridCells - 1;
+        const int hy = cc / kGridS, hx = cc - hy * kGridS;
+        const int gy = gy0 + hy, gx = gx0 + hx;
+        in[u] = (unsigned)gy < (unsigned)op.height && (unsigned)gx < (unsigned)op.width;
+        // row distance <= 21 and width < 2^24 (host checks): 24-bit multiply
+        const uint32_t cell = in[u] ? __umul24((uint32_t)(gy - gyb), (uint32_t)op.width) + (uint32_t)gx : 0u;
+        const TU* src = reinterpret_cast<const TU*>(vb + cell * (uint32_t)(K * sizeof(TU)));
+        if constexpr (sizeof(L) == sizeof(TU)) {
+            load_raw<K>(src, vals[u]);
+        } else {
+            load_row<K>(src, vals[u]);
+        }
+    }
+
     const int maxc = wave_max_nonneg(cnt);
     const int rowbase = wave * kGridS + lane;  // staged cell of window offset (-7, -7)
     constexpr int kCB = K * (int)sizeof(L);    // bytes per staged cell
@@ -194,12 +223,13 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     A z[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) z[k] = (A)0;
-    // chunks stream in groups of U per lane; the loads of the next group are
-    // issued before the current one is consumed (the first group's before the
-    // tile is staged), so each lane keeps U chunks in flight
-    constexpr int U = 2;
-    uint64_t ob[U], obn[U];
-    u32x4 wq[U][NV], wqn[U][NV];
+    // chunks stream in groups of U per lane: the first group is requested
+    // while the halo loads are in flight, so that both wait on memory
+    // together (most wavefronts of a k-nearest-neighbour image graph need no
+    // second group)
+    constexpr int U = 4;
+    uint64_t ob[U];
+    u32x4 wq[U][NV];
     auto fetch = [&](int c) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
@@ -211,69 +241,35 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
             next += __popcll(m);
             if (act) {
                 // streamed once per sweep: keep the staged V halos of other tiles in L2
-                obn[u] = __builtin_nontemporal_load(op.offs + id);
+                ob[u] = __builtin_nontemporal_load(op.offs + id);
 #pragma unroll
-                for (int v = 0; v < NV; ++v) wqn[u][v] = __builtin_nontemporal_load(wv4 + id * NV + v);
+                for (int v = 0; v < NV; ++v) wq[u][v] = __builtin_nontemporal_load(wv4 + id * NV + v);
             }
         }
     };
     fetch(0);
 
-    // stage V over the tile and its halo: every lane issues the loads of its 4
-    // cells at once and zeroes the cells outside the image afterwards.  Loads
-    // use 32-bit byte offsets from the first image row of the halo (the host
-    // keeps 22 rows of V below 2^32 bytes); a cell outside the image loads
-    // that row's first pixel, a valid address.
-    const int gx0 = tx * kGridTX - kGridR, gy0 = ty * kGridTY - kGridR;
-    const int gyb = gy0 < 0 ? 0 : gy0;
-    const unsigned char* vb = reinterpret_cast<const unsigned char*>(V + (int64_t)gyb * op.width * K);
-    for (int c0 = 0; c0 < kGridCells; c0 += 4 * kGridThreads) {
-        L vals[4][K];
-        bool in[4];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = c0 + u * kGridThreads + (int)threadIdx.x;
-            const int cc = c < kGridCells ? c : kGridCells - 1;
-            const int hy = cc / kGridS, hx = cc - hy * kGridS;
-            const int gy = gy0 + hy, gx = gx0 + hx;
-            in[u] = (unsigned)gy < (unsigned)op.height && (unsigned)gx < (unsigned)op.width;
-            // row distance <= 21 and width < 2^24 (host checks): 24-bit multiply
-            const uint32_t cell = in[u] ? __umul24((uint32_t)(gy - gyb), (uint32_t)op.width) + (uint32_t)gx : 0u;
-            const TU* src = reinterpret_cast<const TU*>(vb + cell * (uint32_t)(K * sizeof(TU)));
-            if constexpr (sizeof(L) == sizeof(TU)) {
-                load_raw<K>(src, vals[u]);
+    for (int u = 0; u < 4; ++u) {
+        const int c = u * kGridThreads + (int)threadIdx.x;
+        if (c < kGridCells) {
+            if constexpr ((K * sizeof(L)) % 4 == 0) {
+                // select whole words: all-zero bits are +0 in every field type
+                uint32_t wv[K * sizeof(L) / 4];
+                __builtin_memcpy(wv, vals[u], sizeof(wv));
+#pragma unroll
+                for (int i = 0; i < (int)(K * sizeof(L) / 4); ++i) wv[i] = in[u] ? wv[i] : 0u;
+                __builtin_memcpy(&hv[c * K], wv, sizeof(wv));
             } else {
-                load_row<K>(src, vals[u]);
-            }
-        }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
-            const int c = c0 + u * kGridThreads + (int)threadIdx.x;
-            if (c < kGridCells) {
-                if constexpr ((K * sizeof(L)) % 4 == 0) {
-                    // select whole words: all-zero bits are +0 in every field type
-                    uint32_t wv[K * sizeof(L) / 4];
-                    __builtin_memcpy(wv, vals[u], sizeof(wv));
-#pragma unroll
-                    for (int i = 0; i < (int)(K * sizeof(L) / 4); ++i) wv[i] = in[u] ? wv[i] : 0u;
-                    __builtin_memcpy(&hv[c * K], wv, sizeof(wv));
-                } else {
-#pragma unroll
-                    for (int k = 0; k < K; ++k) hv[c * K + k] = in[u] ? vals[u][k] : store_as<L>::from((A)0);
-                }
+                for (int k = 0; k < K; ++k) hv[c * K + k] = in[u] ? vals[u][k] : store_as<L>::from((A)0);
             }
         }
     }
     __syncthreads();
 
     for (int c = 0; c < maxc; c += U) {
-#pragma unroll
-        for (int u = 0; u < U; ++u) {
-            ob[u] = obn[u];
-#pragma unroll
-            for (int v = 0; v < NV; ++v) wq[u][v] = wqn[u][v];
-        }
-        if (c + U < maxc) fetch(c + U);
+        if (c > 0) fetch(c);
 #pragma unroll
         for (int u = 0; u < U; ++u) {
             if (c + u < cnt) {
