@@ -218,8 +218,13 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     constexpr bool kPacked = (size_t)kGridCells * kCB <= 65536;
     const uint32_t rowb = (uint32_t)rowbase * kCB;
     const unsigned char* hb = static_cast<const unsigned char*>(lds);
-    const u32x4* wv4 = static_cast<const u32x4*>(op.w);
-    int64_t next = wb;
+    // a row segment's chunks are contiguous: address them by 32-bit byte
+    // offsets from the segment's first chunk (at most 64 x 255 chunks)
+    const int64_t wbs = ((int64_t)__builtin_amdgcn_readfirstlane((int)(wb >> 32)) << 32) |
+                        (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wb);
+    const unsigned char* offs_seg = reinterpret_cast<const unsigned char*>(op.offs + wbs);
+    const unsigned char* w_seg = reinterpret_cast<const unsigned char*>(static_cast<const u32x4*>(op.w) + wbs * NV);
+    uint32_t next = 0;  // chunks of the segment dealt so far
     A z[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) z[k] = (A)0;
@@ -236,14 +241,15 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
             const bool act = c + u < cnt;
             const uint64_t m = __ballot(act);
             // rank of this lane among the active ones (mask bits below it)
-            const int64_t id = next + (int64_t)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
-                                                                         __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
-            next += __popcll(m);
+            const uint32_t id = next + __builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32),
+                                                                 __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+            next += (uint32_t)__popcll(m);
             if (act) {
                 // streamed once per sweep: keep the staged V halos of other tiles in L2
-                ob[u] = __builtin_nontemporal_load(op.offs + id);
+                ob[u] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(offs_seg + id * 8u));
+                const u32x4* wp = reinterpret_cast<const u32x4*>(w_seg + id * (uint32_t)(16 * NV));
 #pragma unroll
-                for (int v = 0; v < NV; ++v) wq[u][v] = __builtin_nontemporal_load(wv4 + id * NV + v);
+                for (int v = 0; v < NV; ++v) wq[u][v] = __builtin_nontemporal_load(wp + v);
             }
         }
     };
