@@ -59,6 +59,8 @@ int env_int(const char* name, int dflt) {
 
 }  // namespace
 
+static_assert(gl::kGridDenseMax <= gl::kGridGroup, "the sweep requests the dense chunk rounds as one group");
+
 gl::RowLaunch gl::operator_rows(const gl_operator* op) {
     gl::RowLaunch r = {};
     r.layout = op->layout;
@@ -71,6 +73,7 @@ gl::RowLaunch gl::operator_rows(const gl_operator* op) {
         r.goffs = op->goffs;
         r.gwbase = op->gwbase;
         r.gcnt = op->gcnt;
+        r.gdense = op->gdense;
         r.wheight = op->wheight;
         r.wwidth = op->wwidth;
         r.wtiles_x = op->wtiles_x;
@@ -577,6 +580,7 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         op->wtiles_x = GLy.tiles_x;
         op->nblocks = (int64_t)GLy.tiles_x * ((g->grid_height + gl::kGridTY - 1) / gl::kGridTY);
         op->gchunks = GLy.chunks;
+        op->gdense = GLy.dense;
         op->stored = GLy.chunks * gl::kGridChunk;
         hipError_t e = upload(&d_src, GLy.src, s);
         std::vector<uint64_t> offs64((size_t)GLy.chunks);
@@ -800,6 +804,8 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
             a.op.offs = op->goffs;
             a.op.wbase = op->gwbase;
             a.op.cnt = op->gcnt;
+            a.op.n = op->n;
+            a.op.dense = op->gdense;
             a.op.height = op->wheight;
             a.op.width = op->wwidth;
             a.op.tiles_x = op->wtiles_x;

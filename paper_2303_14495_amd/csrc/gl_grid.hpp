@@ -10,10 +10,14 @@
 // wavefront; the block stages V over the tile and its 7-pixel halo in LDS,
 // K values per cell side by side (one vector LDS read per entry), zeros
 // outside the image.  Chunks are stored so that every wavefront load is
-// contiguous: within a wavefront (a 64-pixel row segment), chunk c of all
-// lanes that have more than c chunks follows chunk c - 1 of all lanes, in
-// lane order; a lane finds its chunk from the wavefront's first chunk, a
-// ballot of the lanes still active and a population count.  A sweep thus
+// contiguous.  The first `dense` chunks of every pixel (dense = the smallest
+// chunk count of the graph, at most 4) are stored by pixel, chunk r of pixel
+// p at r * n + p, so a lane can request them before it knows its chunk count.
+// The others follow by row segment: within a wavefront (a 64-pixel row
+// segment), chunk c of all lanes that have more than c chunks follows chunk
+// c - 1 of all lanes, in lane order; a lane finds its chunk from the
+// segment's first chunk, a ballot of the lanes still active and a population
+// count.  A sweep thus
 // streams 3 bytes per entry in BF16/F16 (1 + 2), plus padding, and no row
 // offsets or halo lists.
 #pragma once
@@ -30,6 +34,7 @@ constexpr int kGridS = kGridTX + 2 * kGridR;      // staged row length, 78
 constexpr int kGridHY = kGridTY + 2 * kGridR;     // staged rows, 22
 constexpr int kGridCells = kGridS * kGridHY;      // 1716
 constexpr int kGridChunk = 8;                     // entries per chunk
+constexpr int kGridGroup = 4;                     // chunks a lane requests at once
 constexpr uint8_t kGridPad = 0x77;                // offset byte of the pixel itself
 constexpr size_t kGridLdsMax = 65536;
 
@@ -38,6 +43,8 @@ struct GridOp {
     const uint64_t* offs;   // [chunks] 8 offset bytes
     const int64_t* wbase;   // [height * tiles_x] first chunk of each wavefront
     const uint8_t* cnt;     // [n] chunks per pixel
+    int64_t n;              // pixels
+    int32_t dense;          // chunk rounds stored by pixel (<= kGridGroup): chunk r of pixel p is r * n + p
     int32_t height, width, tiles_x;
 };
 
@@ -181,6 +188,23 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     const int64_t wb = y < op.height ? op.wbase[(int64_t)y * op.tiles_x + tx] : 0;
     prefetch(ok, p);
 
+    // chunks stream in groups of kGridGroup per lane; the dense rounds of the
+    // first group need only the pixel index and are requested at once
+    constexpr int U = kGridGroup;
+    const u32x4* wv4 = static_cast<const u32x4*>(op.w);
+    uint64_t ob[U];
+    u32x4 wq[U][NV];
+#pragma unroll
+    for (int u = 0; u < U; ++u) {
+        if (u < op.dense && ok) {
+            const int64_t id = (int64_t)u * op.n + p;
+            // streamed once per sweep: keep the staged V halos of other tiles in L2
+            ob[u] = __builtin_nontemporal_load(op.offs + id);
+#pragma unroll
+            for (int v = 0; v < NV; ++v) wq[u][v] = __builtin_nontemporal_load(wv4 + id * NV + v);
+        }
+    }
+
     // stage V over the tile and its halo, in two halves around the first
     // chunk fetch: every lane issues the loads of its 4 cells at once (before
     // waiting for its chunk count), and writes them to LDS afterwards, cells
@@ -223,21 +247,18 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     const int64_t wbs = ((int64_t)__builtin_amdgcn_readfirstlane((int)(wb >> 32)) << 32) |
                         (uint32_t)__builtin_amdgcn_readfirstlane((int)(uint32_t)wb);
     const unsigned char* offs_seg = reinterpret_cast<const unsigned char*>(op.offs + wbs);
-    const unsigned char* w_seg = reinterpret_cast<const unsigned char*>(static_cast<const u32x4*>(op.w) + wbs * NV);
+    const unsigned char* w_seg = reinterpret_cast<const unsigned char*>(wv4 + wbs * NV);
     uint32_t next = 0;  // chunks of the segment dealt so far
     A z[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) z[k] = (A)0;
-    // chunks stream in groups of U per lane: the first group is requested
-    // while the halo loads are in flight, so that both wait on memory
-    // together (most wavefronts of a k-nearest-neighbour image graph need no
-    // second group)
-    constexpr int U = 4;
-    uint64_t ob[U];
-    u32x4 wq[U][NV];
+    // the rounds of group c that are stored by segment; their requests wait
+    // for the chunk count, and are in flight while the first group's dense
+    // rounds are consumed
     auto fetch = [&](int c) {
 #pragma unroll
         for (int u = 0; u < U; ++u) {
+            if (c + u < op.dense) continue;
             const bool act = c + u < cnt;
             const uint64_t m = __ballot(act);
             // rank of this lane among the active ones (mask bits below it)
@@ -245,7 +266,6 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
                                                                  __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
             next += (uint32_t)__popcll(m);
             if (act) {
-                // streamed once per sweep: keep the staged V halos of other tiles in L2
                 ob[u] = __builtin_nontemporal_load(reinterpret_cast<const uint64_t*>(offs_seg + id * 8u));
                 const u32x4* wp = reinterpret_cast<const u32x4*>(w_seg + id * (uint32_t)(16 * NV));
 #pragma unroll

@@ -42,6 +42,7 @@ struct RowLaunch {
     const uint64_t* goffs;
     const int64_t* gwbase;
     const uint8_t* gcnt;
+    int32_t gdense;
 };
 
 struct SweepLaunch {
@@ -89,6 +90,7 @@ struct gl_operator {
     int64_t* gwbase = nullptr;
     uint8_t* gcnt = nullptr;
     int64_t gchunks = 0;
+    int32_t gdense = 0;  // chunk rounds stored by pixel
     size_t bytes = 0;
 };
 

@@ -183,6 +183,8 @@ static GridOp grid_op(const RowLaunch& r) {
     op.offs = r.goffs;
     op.wbase = r.gwbase;
     op.cnt = r.gcnt;
+    op.n = r.n;
+    op.dense = r.gdense;
     op.height = r.wheight;
     op.width = r.wwidth;
     op.tiles_x = r.wtiles_x;
