@@ -350,10 +350,10 @@ gl_status gl_params_validate(const gl_params *params);
 
 /* Measurement helper: launch `reps` sweep kernels exactly as gl_solve launches
  * its sweeps s >= 1 (gathering from one workspace buffer, writing the other,
- * reading u^t = U on the own row, block partial sums on), each bracketed by
- * its own pair of HIP events on `stream`; *avg_ms (host) receives the mean of
- * the pairs' spans, i.e. the kernel time without the gaps between launches.
- * 1 <= reps <= 10000.
+ * reading u^t = U on the own row, block partial sums on), back to back
+ * between one pair of HIP events on `stream`, as a solve issues them; *avg_ms
+ * (host) receives the span divided by reps: the mean time per launch, gaps
+ * between launches included.  1 <= reps <= 10000.
  * U is read, not changed; the workspace contents are overwritten.
  * Synchronises `stream`. */
 gl_status gl_time_sweeps(const gl_operator *op, const gl_params *params, int32_t K,

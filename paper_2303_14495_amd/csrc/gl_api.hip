@@ -1062,25 +1062,22 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     L.ut = ut;
     // seed P with u^t so every timed sweep gathers finite values
     GL_HIP(copy_bytes(ut, P, (size_t)op->n * K * dtype_size(store_u), s), "copy");
-    // one event pair around every launch: the sum of the pairs' spans is the
-    // kernels' own time, without the gaps between back-to-back launches
-    std::vector<hipEvent_t> ev(2 * (size_t)reps, nullptr);
-    hipError_t err = hipSuccess;
-    for (size_t i = 0; i < ev.size() && err == hipSuccess; ++i) err = hipEventCreate(&ev[i]);
+    // back-to-back launches between one event pair, as a solve issues them:
+    // the mean per launch includes the gaps between launches (an event pair
+    // around every launch would add its own completion work to every span)
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t err = hipEventCreate(&ev[0]);
+    if (err == hipSuccess) err = hipEventCreate(&ev[1]);
+    if (err == hipSuccess) err = hipEventRecord(ev[0], s);
     for (int i = 0; i < reps && err == hipSuccess; ++i) {
         L.vin = (i & 1) ? Q : P;
         L.vout = (i & 1) ? P : Q;
-        err = hipEventRecord(ev[2 * i], s);
-        if (err == hipSuccess) err = launch_sweep(store_u, K, L, s);
-        if (err == hipSuccess) err = hipEventRecord(ev[2 * i + 1], s);
+        err = launch_sweep(store_u, K, L, s);
     }
-    if (err == hipSuccess) err = hipEventSynchronize(ev.back());
-    double total = 0.0;
-    for (int i = 0; i < reps && err == hipSuccess; ++i) {
-        float ms = 0.f;
-        err = hipEventElapsedTime(&ms, ev[2 * i], ev[2 * i + 1]);
-        total += ms;
-    }
+    if (err == hipSuccess) err = hipEventRecord(ev[1], s);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
+    float total = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&total, ev[0], ev[1]);
     for (hipEvent_t e : ev)
         if (e) (void)hipEventDestroy(e);
     GL_HIP(err, "timed sweeps");

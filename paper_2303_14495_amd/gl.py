@@ -351,7 +351,8 @@ class Operator:
 
 def time_sweeps(op: Operator, labels: torch.Tensor, U: torch.Tensor, *, eps, c, eta, precond,
                 delta0=1e-6, lambda_max=2.0, step_k=math.inf, reps=20, stream=None) -> float:
-    """Mean duration (ms) of the sweep kernel, timed with HIP events on the stream."""
+    """Mean time per sweep launch (ms): `reps` launches back to back between one
+    pair of HIP events on the stream, gaps between launches included."""
     lib = load_library()
     K = U.shape[1]
     store_u = DTYPE_OF_TORCH[U.dtype]
