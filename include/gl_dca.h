@@ -125,7 +125,7 @@ typedef enum gl_laplacian { GL_LAP_NORMALIZED = 0, GL_LAP_UNNORMALIZED = 1 } gl_
  *            halo of the field in LDS; it takes no `order` and is built on
  *            the host (the CSR pattern is copied back once).  One call with K
  *            columns needs K * 78 * 22 * (field element size: 2, 4 or 8
- *            bytes) <= 65536 of LDS and 22 * grid_width * K * (element
+ *            bytes) <= 147456 of LDS and 22 * grid_width * K * (element
  *            size) < 2^32 bytes, both checked per call (GL_E_INVALID_ARG);
  *            grid_width < 2^24.
  * Every degree d_i = sum_j w_ij must be > 0. */
@@ -222,7 +222,7 @@ typedef struct gl_window_graph {
  * (2r+1)^2 - 1 weights per pixel and no column indices.  The operator serves
  * gl_solve, gl_laplacian_apply, gl_power_max_eig, gl_second_eigenpair and
  * gl_time_sweeps like any other; one call with K columns needs
- * K * (64 + 2r) * (4 + 2r) * (4 or 8 bytes) <= 65536 of LDS, checked per
+ * K * (64 + 2r) * (4 + 2r) * (4 or 8 bytes) <= 147456 of LDS, checked per
  * call (GL_E_INVALID_ARG).  Construction holds 8 bytes per stored entry of
  * temporary device memory.  Synchronises `stream`.  Errors: GL_E_INVALID_ARG,
  * GL_E_BAD_GRAPH (a pixel whose weights all underflow to zero: a degree of

@@ -36,7 +36,7 @@ constexpr int kGridCells = kGridS * kGridHY;      // 1716
 constexpr int kGridChunk = 8;                     // entries per chunk
 constexpr int kGridGroup = 4;                     // chunks a lane requests at once
 constexpr uint8_t kGridPad = 0x77;                // offset byte of the pixel itself
-constexpr size_t kGridLdsMax = 65536;
+constexpr size_t kGridLdsMax = 147456;  // staged tile per block (the device allows 160 KB; room for static LDS)
 
 struct GridOp {
     const void* w;          // [chunks][8] weights
@@ -237,8 +237,8 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     const int maxc = wave_max_nonneg(cnt);
     const int rowbase = wave * kGridS + lane;  // staged cell of window offset (-7, -7)
     constexpr int kCB = K * (int)sizeof(L);    // bytes per staged cell
-    // tiles beyond 64 KB are rejected by the host; their instantiations keep
-    // the 32-bit decode so that they still compile
+    // tiles beyond 64 KB (wide fields, e.g. 16 float columns) keep the 32-bit
+    // offset decode
     constexpr bool kPacked = (size_t)kGridCells * kCB <= 65536;
     const uint32_t rowb = (uint32_t)rowbase * kCB;
     const unsigned char* hb = static_cast<const unsigned char*>(lds);

@@ -29,7 +29,7 @@ constexpr int kWinTX = 64;    // tile width: one wavefront per image row
 constexpr int kWinTY = 4;     // tile height: four wavefronts
 constexpr int kWinMaxR = 27;  // largest window radius (55 x 55 window)
 constexpr int kWinMaxRp = 4;  // largest patch radius (9 x 9 patch)
-constexpr size_t kWinLdsMax = 65536;  // LDS one block may stage (K columns of the halo)
+constexpr size_t kWinLdsMax = 147456;  // LDS one block may stage (the device allows 160 KB; room for static LDS)
 
 struct WinOp {
     const void* w;          // weights, layout above

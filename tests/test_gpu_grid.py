@@ -66,6 +66,27 @@ def test_laplacian_ragged(h, w, store, K):
     assert err <= tol
 
 
+@pytest.mark.parametrize("h,w", [(37, 70), (13, 200)])
+@pytest.mark.parametrize("store,K", [(("f32", "f32"), 16), (("f64", "f64"), 8), (("f16", "f16"), 16),
+                                     (("f32", "f32"), 9)])
+def test_laplacian_wide_fields(h, w, store, K):
+    # staged tiles above 64 KB (f32 K = 16: 110 KB, f64 K = 8, f32 K = 9) take
+    # the 32-bit offset decode; f16 K = 16 (55 KB) the packed one
+    p = _img(h, w)
+    store_w, store_u = store
+    say(f"grid laplacian wide {h}x{w} store={store} K={K}")
+    op = make_operator(p, store_w, layout="grid")
+    rng = np.random.default_rng(h + w + K)
+    X = torch.from_numpy(rng.uniform(-1, 1, (p.n, K))).to(DEV, DT[store_u]).contiguous()
+    Y = op.laplacian_apply(X).to(torch.float64).cpu().numpy()
+    rp, col, ww = p.graph.numpy()
+    ref = gl_oracle.laplacian_apply(p.n, rp, col, ww, X.to(torch.float64).cpu().numpy())
+    tol = {"f64": 1e-13, "f32": 2e-6, "f16": 3e-3}[store_u]
+    err = np.abs(Y - ref).max()
+    say(f"  max err {err:.3e}")
+    assert err <= tol
+
+
 @pytest.mark.parametrize("store", [("f64", "f64"), ("f32", "f32"), ("bf16", "f16")])
 def test_unnormalized_laplacian(store):
     p = _img(37, 70)
@@ -153,6 +174,6 @@ def test_grid_rejections():
                     order=torch.arange(p.n, dtype=torch.int32, device=DEV))
     with pytest.raises(gl.GLError):  # read as a 70 x 37 image the edges leave the window
         gl.Operator(*args, layout="grid", grid=(70, 37))
-    op = gl.Operator(*args, layout="grid", grid=(37, 70), store_w="f32")
-    with pytest.raises(gl.GLError):  # 16 float columns exceed one block's LDS
-        op.laplacian_apply(torch.zeros((p.n, 16), device=DEV))
+    op = gl.Operator(*args, layout="grid", grid=(37, 70), store_w="f64")
+    with pytest.raises(gl.GLError, match="LDS"):  # 16 double columns (215 KB) exceed one block's LDS
+        op.laplacian_apply(torch.zeros((p.n, 16), dtype=torch.float64, device=DEV))

@@ -104,7 +104,7 @@ def test_weights_f64_column_by_column(laplacian):
 def test_laplacian_apply(h, w, rw, store, K):
     p, _ = _problem(h, w, rw)
     store_w, store_u = store
-    if K * (64 + 2 * rw) * (4 + 2 * rw) * (8 if store_u == "f64" else 4) > 65536:
+    if K * (64 + 2 * rw) * (4 + 2 * rw) * (8 if store_u == "f64" else 4) > 147456:
         pytest.skip("K columns exceed the LDS of one block at this radius")
     rp_, col, ww = _graph(p)
     say(f"window laplacian {h}x{w} r={rw} store={store} K={K}")
