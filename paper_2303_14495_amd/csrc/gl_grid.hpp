@@ -48,47 +48,6 @@ struct GridOp {
     int32_t height, width, tiles_x;
 };
 
-// Sum over the 64 lanes of a wavefront in a fixed order, with DPP lane moves
-// (no LDS traffic); the total is valid in lane 63.  Steps: lane ^ 1, lane ^ 2,
-// mirror within 8 lanes, mirror within 16 lanes (every lane then holds its
-// row's sum), rows 1 and 3 add the last lane of rows 0 and 2, rows 2 and 3
-// add lane 31.
-template <int CTRL, int ROWS> __device__ __forceinline__ int dpp_mov(int v) {
-    return __builtin_amdgcn_update_dpp(0, v, CTRL, ROWS, 0xf, false);  // 0 in rows outside ROWS
-}
-
-template <int CTRL, int ROWS, typename A> __device__ __forceinline__ A dpp_add(A x) {
-    if constexpr (sizeof(A) == 4) {
-        return x + __builtin_bit_cast(A, dpp_mov<CTRL, ROWS>(__builtin_bit_cast(int, x)));
-    } else {
-        const uint64_t u = __builtin_bit_cast(uint64_t, x);
-        const uint32_t lo = (uint32_t)dpp_mov<CTRL, ROWS>((int)(uint32_t)u);
-        const uint32_t hi = (uint32_t)dpp_mov<CTRL, ROWS>((int)(uint32_t)(u >> 32));
-        return x + __builtin_bit_cast(A, ((uint64_t)hi << 32) | lo);
-    }
-}
-
-template <typename A> __device__ __forceinline__ A wave_sum63(A x) {
-    x = dpp_add<0xb1, 0xf>(x);   // quad_perm [1, 0, 3, 2]
-    x = dpp_add<0x4e, 0xf>(x);   // quad_perm [2, 3, 0, 1]
-    x = dpp_add<0x141, 0xf>(x);  // row_half_mirror
-    x = dpp_add<0x140, 0xf>(x);  // row_mirror
-    x = dpp_add<0x142, 0xa>(x);  // row_bcast:15 into rows 1 and 3
-    return dpp_add<0x143, 0xc>(x);  // row_bcast:31 into rows 2 and 3
-}
-
-// Largest value of a non-negative int over the wavefront (same steps), as a
-// wave-uniform value.
-__device__ __forceinline__ int wave_max_nonneg(int x) {
-    x = max(x, dpp_mov<0xb1, 0xf>(x));
-    x = max(x, dpp_mov<0x4e, 0xf>(x));
-    x = max(x, dpp_mov<0x141, 0xf>(x));
-    x = max(x, dpp_mov<0x140, 0xf>(x));
-    x = max(x, dpp_mov<0x142, 0xa>(x));
-    x = max(x, dpp_mov<0x143, 0xc>(x));
-    return __builtin_amdgcn_readlane(x, 63);
-}
-
 // Fixed-order block reduction of per-lane column statistics for NW wavefronts
 // (as block_stats, every lane holding all K columns).  with_e = false: the e
 // statistics are known to be zero and are written as such.

@@ -210,7 +210,7 @@ __device__ __forceinline__ void tile_products(const TileOp& op, const TU* __rest
         }
         for (int off = kTileG >> 1; off > 0; off >>= 1) {
 #pragma unroll
-            for (int k = 0; k < K; ++k) z[k] += __shfl_xor(z[k], off, 64);
+            for (int k = 0; k < K; ++k) z[k] = xor_add(z[k], off);
         }
         // this lane finishes columns q, q + 4, ...
         constexpr int CPL = (K + kTileG - 1) / kTileG;
