@@ -915,8 +915,9 @@ gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype sto
     const size_t field = align256((size_t)op->n * K * dtype_size(store_u));
     const size_t acc = store_u == GL_F64 ? 8 : 4;
     // ordered operators keep all three field buffers and the labels in position order
+    // the block partial sums of up to kStatGroup sweeps wait for one reduction
     *bytes = (op->order ? 3 * field + align256((size_t)op->n * 4) : 2 * field) +
-             align256((size_t)2 * K * r.grid * acc);
+             (size_t)gl::kStatGroup * align256((size_t)2 * K * r.grid * acc);
     return GL_OK;
 }
 
@@ -971,16 +972,39 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
     double* res_base = stats ? stats + (int64_t)(T + 1) * K : nullptr;
     if (stats) GL_HIP(fill_double(stats, slen, 0.0, s), "stats init");
 
-    auto finalize = [&](double* e_dst, double* r_dst) -> hipError_t {
-        if (!stats) return hipSuccess;
+    // The statistics of each sweep are reduced later, kStatGroup sweeps per
+    // launch: sweep j of a group writes its block partial sums to set j.
+    const size_t acc = store_u == GL_F64 ? 8 : 4;
+    const size_t set_bytes = align256((size_t)2 * K * L.r.grid * acc);
+    gl::StatGroup group = {};
+    int pending = 0;
+    auto flush = [&]() -> hipError_t {
+        if (!stats || pending == 0) return hipSuccess;
+        const dim3 grid((unsigned)(2 * K), (unsigned)pending);
+        const int64_t stride = (int64_t)(set_bytes / acc);
         if (store_u == GL_F64) {
-            hipLaunchKernelGGL(gl::finalize_stats_kernel<double>, dim3(2 * K), dim3(256), 0, s,
-                               (const double*)partials, L.r.grid, K, e_dst, r_dst, flag);
+            hipLaunchKernelGGL(gl::finalize_group_kernel<double>, grid, dim3(256), 0, s,
+                               (const double*)partials, L.r.grid, stride, K, group, flag);
         } else {
-            hipLaunchKernelGGL(gl::finalize_stats_kernel<float>, dim3(2 * K), dim3(256), 0, s,
-                               (const float*)partials, L.r.grid, K, e_dst, r_dst, flag);
+            hipLaunchKernelGGL(gl::finalize_group_kernel<float>, grid, dim3(256), 0, s,
+                               (const float*)partials, L.r.grid, stride, K, group, flag);
         }
+        pending = 0;
+        group = {};
         return hipGetLastError();
+    };
+    // before a sweep: point it at the next free set (reducing a full group first)
+    auto next_set = [&](double* e_dst, double* r_dst) -> hipError_t {
+        if (!stats) return hipSuccess;
+        if (pending == gl::kStatGroup) {
+            hipError_t e = flush();
+            if (e != hipSuccess) return e;
+        }
+        L.partials = (char*)partials + (size_t)pending * set_bytes;
+        group.energy_dst[pending] = e_dst;
+        group.res_dst[pending] = r_dst;
+        ++pending;
+        return hipSuccess;
     };
 
     int cur = 0;  // buffer holding u^t
@@ -993,10 +1017,10 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
             L.vin = bufs[prev];
             L.vout = bufs[outb];
             L.energy = (stats && sw == 0) ? 1 : 0;
-            GL_HIP(launch_sweep(store_u, K, L, s), "sweep launch");
-            GL_HIP(finalize(sw == 0 ? stats + (int64_t)t * K : nullptr,
+            GL_HIP(next_set(sw == 0 ? stats + (int64_t)t * K : nullptr,
                             res_base ? res_base + ((int64_t)t * m + sw) * K : nullptr),
-                   "stats launch");
+                   "stats set");
+            GL_HIP(launch_sweep(store_u, K, L, s), "sweep launch");
             prev = outb;
         }
         cur = prev;
@@ -1007,9 +1031,10 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
         L.vin = bufs[cur];
         L.vout = nullptr;
         L.energy = 1;
+        GL_HIP(next_set(stats + (int64_t)T * K, nullptr), "stats set");
         GL_HIP(launch_sweep(store_u, K, L, s), "energy launch");
-        GL_HIP(finalize(stats + (int64_t)T * K, nullptr), "stats launch");
     }
+    GL_HIP(flush(), "stats launch");
     if (op->order)
         GL_HIP(permute_rows(op, row, bufs[cur], U, true, s), "result scatter");
     else if (cur != 0)

@@ -209,15 +209,24 @@ __device__ __forceinline__ double block_sum(const P* __restrict__ src, int64_t n
     return ((sh[0] + sh[1]) + sh[2]) + sh[3];
 }
 
-// Solve statistics: block s < K -> energy column s, block K + k -> |r|^2 of column k.
+// Solve statistics of up to kStatGroup sweeps, reduced by one launch: set j
+// (block column j) holds the 2K statistics of one sweep at partials + j *
+// stride; block s < K sums energy column s into energy_dst[j][s] (nullptr:
+// none), block K + k the |r|^2 of column k into res_dst[j][k], each in the
+// fixed order of block_sum.  A non-finite sum sets *flag to 1.
+constexpr int kStatGroup = 16;
+struct StatGroup {
+    double* energy_dst[kStatGroup];
+    double* res_dst[kStatGroup];
+};
+
 template <typename P>
-__global__ __launch_bounds__(kBlock) void finalize_stats_kernel(const P* partials, int64_t nb, int32_t K,
-                                                                 double* energy_dst, double* res_dst,
-                                                                 double* flag) {
-    const int s = blockIdx.x;
-    double* dst = s < K ? energy_dst : res_dst;
+__global__ __launch_bounds__(kBlock) void finalize_group_kernel(const P* partials, int64_t nb, int64_t stride,
+                                                                int32_t K, StatGroup g, double* flag) {
+    const int s = blockIdx.x, j = blockIdx.y;
+    double* dst = s < K ? g.energy_dst[j] : g.res_dst[j];
     if (dst == nullptr) return;  // uniform per block
-    const double v = block_sum(partials + (int64_t)s * nb, nb);
+    const double v = block_sum(partials + (int64_t)j * stride + (int64_t)s * nb, nb);
     if (threadIdx.x == 0) {
         dst[s < K ? s : s - K] = v;
         if (!(fabs(v) <= 1.7976931348623157e308)) *flag = 1.0;
