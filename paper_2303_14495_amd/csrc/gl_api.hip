@@ -12,6 +12,7 @@
 #include "gl_internal.hpp"
 #include "gl_kernels.hpp"
 #include "gl_layout.hpp"
+#include "gl_sched.hpp"
 #include "gl_tile.hpp"
 #include "gl_window.hpp"
 #include "gl_grid.hpp"
@@ -456,17 +457,16 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         delete op;
         return fail(GL_E_HIP, "hipGetDevice failed");
     }
-    // geometry of the direct row kernels: G lanes per row from the mean row length
-    const double avg = (double)g->nnz / (double)g->n;
-    int G = 4;
-    while (G < 64 && 2.0 * G <= avg) G *= 2;
-    G = env_int("GL_LANES_PER_ROW", G);
-    if (G < 4 || G > 64 || (G & (G - 1))) G = 16;
+    // geometry of the direct row kernels (shared with the server), with
+    // overrides for experiments
+    const gl::DirectGeom geom = gl::direct_geometry(g->n, g->nnz);
+    int G = env_int("GL_LANES_PER_ROW", geom.G);
+    if (G < 4 || G > 64 || (G & (G - 1))) G = geom.G;
     op->G = G;
     op->log2G = 0;
     while ((1 << op->log2G) < G) ++op->log2G;
-    op->tiles = env_int("GL_TILES_PER_BLOCK", 4);
-    if (op->tiles < 1 || op->tiles > 64) op->tiles = 4;
+    op->tiles = env_int("GL_TILES_PER_BLOCK", geom.tiles);
+    if (op->tiles < 1 || op->tiles > 64) op->tiles = geom.tiles;
     op->remap = env_int("GL_XCD_REMAP", 1) ? 1 : 0;
 
     void* scratch = nullptr;  // [int32 flags][pad][u64 first_bad]

@@ -53,8 +53,14 @@ int main() {
     // geometry
     gl::DirectGeom g = gl::direct_geometry(1000, 15000);
     CHECK(g.G == 4 || g.G == 8);
-    CHECK(g.rows_per_block == (256 / g.G) * 4 && g.blocks * g.rows_per_block >= 1000);
+    // a small graph: one pass per block, so that there are as many blocks as rows allow
+    CHECK(g.tiles == 1 && g.rows_per_block == 256 / g.G && g.blocks * g.rows_per_block >= 1000);
     CHECK(gl::direct_geometry(100, 3000).G == 16);
+    // a large one keeps 4 passes per block (>= 1024 blocks either way)
+    gl::DirectGeom big = gl::direct_geometry(4194304, 92865744);
+    CHECK(big.G == 16 && big.tiles == 4 && big.rows_per_block == 64 && big.blocks == 65536);
+    gl::DirectGeom mid = gl::direct_geometry(70000, 1000000);  // 32 rows per pass
+    CHECK(mid.G == 8 && mid.tiles == 2 && mid.blocks == 1094);  // 4 passes: 547 blocks
 
     // footprint grows with every size and separates the raw CSR copy
     gl::Footprint f1 = gl::served_footprint(10000, 150000, 3, 20, 4, 2, 2);
