@@ -214,7 +214,8 @@ __device__ __forceinline__ int wave_max_nonneg(int x) {
 // x + x of lane (lane ^ off), the partner's value added to this lane's: a DPP
 // quad permute for off = 1 and 2 (the same lane pairs as the shuffle, without
 // an LDS permute; every lane of the wavefront must be active), the shuffle
-// otherwise.
+// otherwise.  For compile-time offsets only: with a run-time offset the tests
+// cost more than the permutes save.
 template <typename A> __device__ __forceinline__ A xor_add(A x, int off) {
     if (off == 1) return dpp_add<0xb1, 0xf>(x);
     if (off == 2) return dpp_add<0x4e, 0xf>(x);
@@ -254,7 +255,7 @@ __device__ __forceinline__ void row_gather(const OffT* __restrict__ rp, const in
     }
     for (int off = G >> 1; off > 0; off >>= 1) {
 #pragma unroll
-        for (int k = 0; k < K; ++k) z[k] = xor_add(z[k], off);
+        for (int k = 0; k < K; ++k) z[k] += __shfl_xor(z[k], off, 64);
     }
 }
 
@@ -269,8 +270,8 @@ __device__ __forceinline__ void block_stats(A (&e)[CPL], A (&r)[CPL], int G, A* 
     for (int off = G; off < 64; off <<= 1) {
 #pragma unroll
         for (int c = 0; c < CPL; ++c) {
-            e[c] = xor_add(e[c], off);
-            r[c] = xor_add(r[c], off);
+            e[c] += __shfl_xor(e[c], off, 64);
+            r[c] += __shfl_xor(r[c], off, 64);
         }
     }
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;

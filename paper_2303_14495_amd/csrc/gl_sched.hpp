@@ -76,8 +76,9 @@ class Arena {
 
 // Direct-layout geometry for a graph: G lanes per row (smallest power of two
 // with 2G > mean row length, 4..64), 4 passes of 256/G rows per block, or 2
-// or 1 when that would leave fewer than 1024 blocks (four per compute unit)
-// for a small graph.  Every row is summed in the same order whatever the
+// or 1 when that would leave fewer than 256 blocks (one per compute unit)
+// for a small graph (more, shorter blocks cost the batched server more than
+// they gain above that).  Every row is summed in the same order whatever the
 // geometry; the block partial sums of the statistics follow it, so gl_solve
 // and the server share this function.
 struct DirectGeom {
@@ -95,7 +96,7 @@ inline DirectGeom direct_geometry(int64_t n, int64_t nnz) {
     while ((1 << g.log2G) < G) ++g.log2G;
     const int64_t rows_per_tile = (int64_t)(256 >> g.log2G);
     g.tiles = 4;
-    while (g.tiles > 1 && (n + rows_per_tile * g.tiles - 1) / (rows_per_tile * g.tiles) < 1024) g.tiles /= 2;
+    while (g.tiles > 1 && (n + rows_per_tile * g.tiles - 1) / (rows_per_tile * g.tiles) < 256) g.tiles /= 2;
     g.rows_per_block = rows_per_tile * g.tiles;
     g.blocks = (n + g.rows_per_block - 1) / g.rows_per_block;
     return g;

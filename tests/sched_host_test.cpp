@@ -60,7 +60,9 @@ int main() {
     gl::DirectGeom big = gl::direct_geometry(4194304, 92865744);
     CHECK(big.G == 16 && big.tiles == 4 && big.rows_per_block == 64 && big.blocks == 65536);
     gl::DirectGeom mid = gl::direct_geometry(70000, 1000000);  // 32 rows per pass
-    CHECK(mid.G == 8 && mid.tiles == 2 && mid.blocks == 1094);  // 4 passes: 547 blocks
+    CHECK(mid.G == 8 && mid.tiles == 4 && mid.blocks == 547);
+    gl::DirectGeom small = gl::direct_geometry(4096, 61000);  // 4 passes: 32 blocks
+    CHECK(small.G == 8 && small.tiles == 1 && small.blocks == 128);
 
     // footprint grows with every size and separates the raw CSR copy
     gl::Footprint f1 = gl::served_footprint(10000, 150000, 3, 20, 4, 2, 2);
