@@ -27,7 +27,7 @@ class _Img:
         img, truth = rectangles_image(h, w, 4, rng, side=(4, 20), noise=0.1)
         feat = torch.from_numpy(patch_features(img, 3))
         nbr = window_knn(feat, k, radius=7)
-        self.graph = self_tuning_graph(feat.view(h * w, -1), nbr)
+        self.graph = self_tuning_graph(feat.view(h * w, -1), nbr, scale_rank=min(7, k))
         self.n = h * w
         self.extra = {"grid": (h, w)}
         self.truth = truth.reshape(-1)
@@ -85,6 +85,30 @@ def test_laplacian_wide_fields(h, w, store, K):
     err = np.abs(Y - ref).max()
     say(f"  max err {err:.3e}")
     assert err <= tol
+
+
+@pytest.mark.parametrize("k", [4, 30])
+@pytest.mark.parametrize("K", [1, 4])
+def test_dense_chunk_rounds(k, K):
+    # every pixel's first min(smallest chunk count, 4) chunks are stored by
+    # pixel: k = 4 leaves one such round (degrees from 4), k = 30 the most, four
+    h, w = 37, 70
+    key = (h, w, k)
+    if key not in _G:
+        _G[key] = _Img(h, w, k=k, seed=7)
+    p = _G[key]
+    rp, col, ww = p.graph.numpy()
+    deg = np.diff(rp)
+    rounds = min(int((deg.min() + 7) // 8), 4)
+    assert rounds == (1 if k == 4 else 4)
+    op = make_operator(p, "f32", layout="grid")
+    rng = np.random.default_rng(k + K)
+    X = torch.from_numpy(rng.uniform(-1, 1, (p.n, K))).to(DEV, torch.float32).contiguous()
+    Y = op.laplacian_apply(X).to(torch.float64).cpu().numpy()
+    ref = gl_oracle.laplacian_apply(p.n, rp, col, ww, X.to(torch.float64).cpu().numpy())
+    err = np.abs(Y - ref).max()
+    say(f"grid dense rounds k={k} K={K}: max err {err:.3e}")
+    assert err <= 2e-6
 
 
 @pytest.mark.parametrize("store", [("f64", "f64"), ("f32", "f32"), ("bf16", "f16")])
