@@ -632,7 +632,8 @@ def main():
         "data": "synthetic",
         "config": {"workload": p.name, "n": p.n, "nnz": g.nnz, "K": p.K,
                    "outer_steps": p.outer, "sweeps": p.sweeps, "precond": p.precond,
-                   "eps": p.eps, "c": p.c, "eta": p.eta, "labelled_fraction": 0.005},
+                   "eps": p.eps, "c": p.c, "eta": p.eta,
+                   "labelled_fraction": float(np.mean(p.labels >= 0))},
         "sweep_gbps": achieved,
         "sweep_kernel_ms": main_res["sweep_kernel_ms"],
         "per_graph_setup_ms": {"operator_create": main_res["operator_create_ms"],

@@ -53,10 +53,6 @@ size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
 bool aligned(const void* p, size_t a) { return ((uintptr_t)p % a) == 0; }
 
-int env_int(const char* name, int dflt) {
-    const char* v = std::getenv(name);
-    return (v && *v) ? std::atoi(v) : dflt;
-}
 
 }  // namespace
 
@@ -267,6 +263,7 @@ void launch_normalize_out(gl_operator* op, const gl_graph* g, hipStream_t s) {
 
 void free_op(gl_operator* op) {
     if (!op) return;
+    op->magic = 0;
     (void)hipFree(op->order);
     (void)hipFree(op->rp);
     (void)hipFree(op->col);
@@ -457,17 +454,13 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         delete op;
         return fail(GL_E_HIP, "hipGetDevice failed");
     }
-    // geometry of the direct row kernels (shared with the server), with
-    // overrides for experiments
+    // geometry of the direct row kernels: the same function as the server's,
+    // so a served solve sums every row and block in the order gl_solve does
     const gl::DirectGeom geom = gl::direct_geometry(g->n, g->nnz);
-    int G = env_int("GL_LANES_PER_ROW", geom.G);
-    if (G < 4 || G > 64 || (G & (G - 1))) G = geom.G;
-    op->G = G;
-    op->log2G = 0;
-    while ((1 << op->log2G) < G) ++op->log2G;
-    op->tiles = env_int("GL_TILES_PER_BLOCK", geom.tiles);
-    if (op->tiles < 1 || op->tiles > 64) op->tiles = geom.tiles;
-    op->remap = env_int("GL_XCD_REMAP", 1) ? 1 : 0;
+    op->G = geom.G;
+    op->log2G = geom.log2G;
+    op->tiles = geom.tiles;
+    op->remap = 1;
 
     void* scratch = nullptr;  // [int32 flags][pad][u64 first_bad]
     if (hipMalloc((void**)&op->degree, (size_t)g->n * 8) != hipSuccess || hipMalloc(&scratch, 64) != hipSuccess) {
@@ -685,13 +678,15 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
 gl_status gl_params_validate(const gl_params* params) { return check_params(params); }
 
 gl_status gl_operator_destroy(gl_operator* op) {
+    if (!op) return GL_OK;
+    if (!gl::valid(op)) return fail(GL_E_INVALID_ARG, "not an operator handle");
     free_op(op);
     return GL_OK;
 }
 
 gl_status gl_operator_info(const gl_operator* op, int64_t* n, int64_t* nnz, gl_dtype* store_w,
                            int32_t* lanes_per_row, size_t* device_bytes) {
-    if (!op) return fail(GL_E_INVALID_ARG, "operator is NULL");
+    if (!gl::valid(op)) return fail(GL_E_INVALID_ARG, "operator is NULL or not an operator handle");
     if (n) *n = op->n;
     if (nnz) *nnz = op->nnz;
     if (store_w) *store_w = op->store_w;
@@ -702,7 +697,7 @@ gl_status gl_operator_info(const gl_operator* op, int64_t* n, int64_t* nnz, gl_d
 
 gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* stored, int32_t* halo_max,
                              int64_t* halo_total, int64_t* stream_bytes) {
-    if (!op) return fail(GL_E_INVALID_ARG, "operator is NULL");
+    if (!gl::valid(op)) return fail(GL_E_INVALID_ARG, "operator is NULL or not an operator handle");
     const bool tile = op->layout == gl::LAYOUT_TILE;
     if (op->layout == gl::LAYOUT_GRID) {
         if (layout) *layout = GL_LAYOUT_GRID;
@@ -741,7 +736,7 @@ gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* st
 
 gl_status gl_laplacian_apply(const gl_operator* op, int32_t K, gl_dtype dtype, const void* X, void* Y,
                              void* stream) {
-    if (!op || !X || !Y) return fail(GL_E_INVALID_ARG, "operator, X and Y must not be NULL");
+    if (!gl::valid(op) || !X || !Y) return fail(GL_E_INVALID_ARG, "operator (a live operator handle), X and Y must not be NULL");
     if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
     if (!pair_ok(op->store_w, dtype)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
     if (!aligned(X, 16) || !aligned(Y, 16)) return fail(GL_E_INVALID_ARG, "X and Y must be 16-byte aligned");
@@ -770,7 +765,7 @@ gl_status gl_laplacian_apply(const gl_operator* op, int32_t K, gl_dtype dtype, c
 }
 
 gl_status gl_power_workspace_size(const gl_operator* op, size_t* bytes) {
-    if (!op || !bytes) return fail(GL_E_INVALID_ARG, "operator and bytes must not be NULL");
+    if (!gl::valid(op) || !bytes) return fail(GL_E_INVALID_ARG, "operator (a live operator handle) and bytes must not be NULL");
     const gl::RowLaunch r = row_launch(op);
     *bytes = (op->order ? 3 : 2) * align256((size_t)op->n * 4) + align256((size_t)2 * r.grid * 4) + 256;
     return GL_OK;
@@ -778,7 +773,7 @@ gl_status gl_power_workspace_size(const gl_operator* op, size_t* bytes) {
 
 gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0, void* ws, size_t ws_bytes,
                            double* rayleigh, double* lambda_hat, void* stream) {
-    if (!op || !x0 || !ws || !rayleigh || !lambda_hat)
+    if (!gl::valid(op) || !x0 || !ws || !rayleigh || !lambda_hat)
         return fail(GL_E_INVALID_ARG, "operator, x0, workspace and outputs must not be NULL");
     if (iters < 0) return fail(GL_E_INVALID_ARG, "iters must be >= 0");
     if (op->store_w == GL_F64) return fail(GL_E_DTYPE, "the power method runs on F32/BF16/F16 weights");
@@ -908,7 +903,7 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
 }
 
 gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype store_u, size_t* bytes) {
-    if (!op || !bytes) return fail(GL_E_INVALID_ARG, "operator and bytes must not be NULL");
+    if (!gl::valid(op) || !bytes) return fail(GL_E_INVALID_ARG, "operator (a live operator handle) and bytes must not be NULL");
     if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
     if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
     const gl::RowLaunch r = row_launch(op);
@@ -923,7 +918,7 @@ gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype sto
 
 gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
                    gl_dtype store_u, void* U, void* ws, size_t ws_bytes, double* stats, void* stream) {
-    if (!op || !labels || !U || !ws) return fail(GL_E_INVALID_ARG, "operator, labels, U and workspace must not be NULL");
+    if (!gl::valid(op) || !labels || !U || !ws) return fail(GL_E_INVALID_ARG, "operator (a live operator handle), labels, U and workspace must not be NULL");
     gl_status st = check_params(params);
     if (st != GL_OK) return st;
     if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
@@ -1045,7 +1040,7 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
 gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
                          gl_dtype store_u, const void* U, void* ws, size_t ws_bytes, int32_t reps, double* avg_ms,
                          void* stream) {
-    if (!op || !labels || !U || !ws || !avg_ms) return fail(GL_E_INVALID_ARG, "NULL argument");
+    if (!gl::valid(op) || !labels || !U || !ws || !avg_ms) return fail(GL_E_INVALID_ARG, "NULL argument or not an operator handle");
     gl_status st = check_params(params);
     if (st != GL_OK) return st;
     if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");

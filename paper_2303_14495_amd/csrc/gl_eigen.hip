@@ -235,7 +235,7 @@ void tridiag_smallest(const std::vector<double>& a, const std::vector<double>& b
 extern "C" {
 
 gl_status gl_second_eigenpair_workspace_size(const gl_operator* op, int32_t krylov, size_t* bytes) {
-    if (!op || !bytes) return efail(GL_E_INVALID_ARG, "operator and bytes must not be NULL");
+    if (!gl::valid(op) || !bytes) return efail(GL_E_INVALID_ARG, "operator (a live operator handle) and bytes must not be NULL");
     if (krylov < 2 || krylov > 512) return efail(GL_E_INVALID_ARG, "krylov must lie in [2, 512]");
     *bytes = carve(op, krylov, nullptr).bytes;
     return GL_OK;
@@ -244,7 +244,7 @@ gl_status gl_second_eigenpair_workspace_size(const gl_operator* op, int32_t kryl
 gl_status gl_second_eigenpair(const gl_operator* op, int32_t krylov, int32_t max_restarts, double tol,
                               const float* x0, float* v_out, void* ws, size_t ws_bytes, double* lambda2,
                               double* residual, int32_t* restarts_used, void* stream) {
-    if (!op || !x0 || !v_out || !ws || !lambda2 || !residual)
+    if (!gl::valid(op) || !x0 || !v_out || !ws || !lambda2 || !residual)
         return efail(GL_E_INVALID_ARG, "operator, x0, v_out, workspace and outputs must not be NULL");
     if (krylov < 2 || krylov > 512) return efail(GL_E_INVALID_ARG, "krylov must lie in [2, 512]");
     if (max_restarts < 0) return efail(GL_E_INVALID_ARG, "max_restarts must be >= 0");

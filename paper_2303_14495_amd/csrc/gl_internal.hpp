@@ -61,6 +61,9 @@ struct SweepLaunch {
 
 // The operator behind the gl_operator handle (library-owned device memory).
 struct gl_operator {
+    // tag checked by every entry point that takes an operator, so that a
+    // server handle (or a destroyed operator) passed in its place is rejected
+    uint64_t magic = 0x6f70657261746f72ull;  // "operator"
     int64_t n = 0, nnz = 0, stored = 0;
     int device = 0;
     gl_dtype store_w = GL_F32;
@@ -95,6 +98,11 @@ struct gl_operator {
 };
 
 namespace gl {
+
+constexpr uint64_t kOperatorMagic = 0x6f70657261746f72ull;
+
+// True for a live operator handle (not NULL, not another handle type).
+inline bool valid(const gl_operator* op) { return op != nullptr && op->magic == kOperatorMagic; }
 
 // Row-kernel launch description of an operator.
 RowLaunch operator_rows(const gl_operator* op);

@@ -238,7 +238,12 @@ double precond_g(int kind, double lam, const gl_params& p) {
 
 }  // namespace
 
+constexpr uint64_t kServerMagic = 0x7365727665722121ull;  // "server!!"
+
 struct gl_server {
+    // tag checked by every entry point that takes a server (an operator
+    // handle, or a destroyed server, passed in its place is rejected)
+    uint64_t magic = kServerMagic;
     gl_server_config cfg{};
     int device = 0;
     std::chrono::steady_clock::time_point t0;
@@ -697,6 +702,10 @@ struct gl_server {
     }
 };
 
+namespace {
+bool srv_ok(const gl_server* srv) { return srv != nullptr && srv->magic == kServerMagic; }
+}  // namespace
+
 extern "C" {
 
 gl_status gl_server_create(const gl_server_config* cfg, gl_server** out) {
@@ -747,7 +756,8 @@ gl_status gl_server_create(const gl_server_config* cfg, gl_server** out) {
 }
 
 gl_status gl_server_submit(gl_server* srv, const gl_request* r, uint64_t* ticket) {
-    if (!srv || !r || !ticket) return sfail(GL_E_INVALID_ARG, "server, request and ticket must not be NULL");
+    if (!srv_ok(srv) || !r || !ticket)
+        return sfail(GL_E_INVALID_ARG, "server (a live server handle), request and ticket must not be NULL");
     if (!r->row_ptr || !r->col_idx || !r->weight || !r->labels || !r->u0)
         return sfail(GL_E_INVALID_ARG, "request arrays must not be NULL");
     if (r->n < 2 || r->n > INT32_MAX || r->nnz < 1 || r->nnz > INT32_MAX)
@@ -802,7 +812,7 @@ gl_status gl_server_submit(gl_server* srv, const gl_request* r, uint64_t* ticket
 }
 
 gl_status gl_server_poll(gl_server* srv, uint64_t ticket, int32_t wait, gl_result* out) {
-    if (!srv || !out) return sfail(GL_E_INVALID_ARG, "server and result must not be NULL");
+    if (!srv_ok(srv) || !out) return sfail(GL_E_INVALID_ARG, "server (a live server handle) and result must not be NULL");
     std::shared_ptr<Solve> s;
     {
         std::unique_lock<std::mutex> g(srv->mu);
@@ -829,7 +839,7 @@ gl_status gl_server_poll(gl_server* srv, uint64_t ticket, int32_t wait, gl_resul
 }
 
 gl_status gl_server_cancel(gl_server* srv, uint64_t ticket) {
-    if (!srv) return sfail(GL_E_INVALID_ARG, "server must not be NULL");
+    if (!srv_ok(srv)) return sfail(GL_E_INVALID_ARG, "server must be a live server handle");
     std::lock_guard<std::mutex> g(srv->mu);
     auto it = srv->all.find(ticket);
     if (it == srv->all.end()) return sfail(GL_E_INVALID_ARG, "unknown or consumed ticket");
@@ -864,7 +874,7 @@ gl_status gl_server_request_bytes(int64_t n, int64_t nnz, int32_t K, int32_t out
 
 gl_status gl_server_info(gl_server* srv, int64_t* pending, int64_t* active, int64_t* finished, size_t* arena_used,
                          int64_t* ticks) {
-    if (!srv) return sfail(GL_E_INVALID_ARG, "server must not be NULL");
+    if (!srv_ok(srv)) return sfail(GL_E_INVALID_ARG, "server must be a live server handle");
     std::lock_guard<std::mutex> g(srv->mu);
     if (pending) *pending = (int64_t)srv->pending.size();
     if (active) *active = srv->slots_used;
@@ -877,6 +887,7 @@ gl_status gl_server_info(gl_server* srv, int64_t* pending, int64_t* active, int6
 
 gl_status gl_server_destroy(gl_server* srv) {
     if (!srv) return GL_OK;
+    if (!srv_ok(srv)) return sfail(GL_E_INVALID_ARG, "not a server handle");
     {
         std::lock_guard<std::mutex> g(srv->mu);
         srv->stop = true;
@@ -906,6 +917,7 @@ gl_status gl_server_destroy(gl_server* srv) {
     (void)hipStreamDestroy(srv->s_fin);
     for (int i = 0; i < gl::kServedMaxTicks; ++i)
         if (srv->tick_ev[i]) (void)hipEventDestroy(srv->tick_ev[i]);
+    srv->magic = 0;
     delete srv;
     return GL_OK;
 }

@@ -488,44 +488,6 @@ class Server:
         return dict(zip(("pending", "active", "finished", "arena_used", "ticks"),
                         [x.value for x in v]))
 
-    @classmethod
-    def window(cls, image: torch.Tensor, window_radius: int = 7, patch_radius: int = 2,
-               sigma: float | None = None, store_w: str = "f32", laplacian: str = "normalized",
-               stream=None) -> "Operator":
-        """Operator of the paper's image graph (Section 2.2), built on the GPU:
-        every pixel joined to its (2 window_radius + 1)^2 - 1 window neighbours
-        with patch-similarity weights over (2 patch_radius + 1)^2 patches.
-        image: CUDA float32 [h, w] or [h, w, channels], row-major pixels (the
-        nodes).  sigma defaults to log(h w) + 1."""
-        lib = load_library()
-        if not image.is_cuda:
-            raise ValueError("image must live on the GPU")
-        img = image.to(torch.float32).contiguous()
-        if img.dim() == 2:
-            img = img.unsqueeze(-1)
-        if img.dim() != 3:
-            raise ValueError("image must be [h, w] or [h, w, channels]")
-        h, w, ch = (int(v) for v in img.shape)
-        if sigma is None:
-            sigma = math.log(h * w) + 1.0
-        g = _WindowGraph(img.data_ptr(), h, w, ch, int(window_radius), int(patch_radius),
-                         LAPLACIANS[laplacian], float(sigma), 0)
-        self = cls.__new__(cls)
-        self._h = None
-        handle = ctypes.c_void_p()
-        _check(lib.gl_window_operator_create(ctypes.byref(g), DTYPES[store_w],
-                                             _stream_handle(stream), ctypes.byref(handle)))
-        self._h = handle
-        self._ws = {}
-        self.row_ptr = self.col = self.weight = None
-        self.store_w = store_w
-        self.device = image.device
-        self.laplacian = laplacian
-        self.n = h * w
-        self.nnz = self.info()["nnz"]
-        self.image_shape = (h, w)
-        return self
-
     def close(self):
         if getattr(self, "_h", None) is not None:
             load_library().gl_server_destroy(self._h)

@@ -181,3 +181,53 @@ def test_grid_operator_rejects_order():
     out = ctypes.c_void_p()
     assert lib.gl_operator_create(ctypes.byref(g), 1, None, ctypes.byref(out)) == 1
     assert b"order" in lib.gl_last_error()
+
+
+def _fake_handle(magic: int):
+    """A host buffer standing in for a handle of another type: only its first
+    8 bytes (the type tag) are read before the entry point rejects it."""
+    buf = ctypes.create_string_buffer(4096)
+    ctypes.memmove(buf, int(magic).to_bytes(8, "little"), 8)
+    return buf
+
+
+@pytest.mark.parametrize("magic", [0, 0x7365727665722121, 0x6f70657261746f72 ^ 1])
+def test_operator_entry_points_reject_foreign_handles(magic):
+    # a server handle (its tag), a zeroed block or a near miss where an
+    # operator is expected: rejected, nothing freed or launched
+    lib = gl.load_library()
+    buf = _fake_handle(magic)
+    h = ctypes.cast(buf, ctypes.c_void_p)
+    n = ctypes.c_int64()
+    assert lib.gl_operator_info(h, ctypes.byref(n), None, None, None, None) == 1
+    assert lib.gl_operator_layout(h, None, None, None, None, None) == 1
+    nb = ctypes.c_size_t()
+    assert lib.gl_solve_workspace_size(h, 1, 1, ctypes.byref(nb)) == 1
+    assert lib.gl_power_workspace_size(h, ctypes.byref(nb)) == 1
+    fake = ctypes.c_void_p(4096)
+    p = _params()
+    assert lib.gl_solve(h, ctypes.byref(p), 1, fake, 1, fake, fake, 1 << 20, None, None) == 1
+    assert lib.gl_laplacian_apply(h, 1, 1, fake, fake, None) == 1
+    assert lib.gl_operator_destroy(h) == 1
+    assert b"operator" in lib.gl_last_error()
+    # the buffer was not freed or modified
+    assert int.from_bytes(buf.raw[:8], "little") == magic
+
+
+@pytest.mark.parametrize("magic", [0, 0x6f70657261746f72])
+def test_server_entry_points_reject_foreign_handles(magic):
+    # an operator handle (its tag) or a zeroed block where a server is expected
+    lib = gl.load_library()
+    buf = _fake_handle(magic)
+    h = ctypes.cast(buf, ctypes.c_void_p)
+    v = [ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64(), ctypes.c_size_t(), ctypes.c_int64()]
+    assert lib.gl_server_info(h, *[ctypes.byref(x) for x in v]) == 1
+    assert lib.gl_server_cancel(h, 1) == 1
+    res = glmod._Result()
+    assert lib.gl_server_poll(h, 1, 0, ctypes.byref(res)) == 1
+    req = glmod._Request()
+    t = ctypes.c_uint64()
+    assert lib.gl_server_submit(h, ctypes.byref(req), ctypes.byref(t)) == 1
+    assert lib.gl_server_destroy(h) == 1
+    assert b"server" in lib.gl_last_error()
+    assert int.from_bytes(buf.raw[:8], "little") == magic
