@@ -344,6 +344,24 @@ gl_status gl_solve(const gl_operator *op, const gl_params *params, int32_t K,
                    const int32_t *labels, gl_dtype store_u, void *U,
                    void *workspace, size_t workspace_bytes, double *stats, void *stream);
 
+/* gl_solve without a workspace argument, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, harnesses
+ * that forbid hipMalloc.  Arguments, results and errors as gl_solve; the
+ * workspace is a static device array of the library (128 MiB, one copy on
+ * each GPU the library's kernels are loaded on, held until the process
+ * ends).  The call itself allocates nothing and never synchronises; its
+ * first call on a device resolves the array's address (make it outside a
+ * graph capture).  Solves whose gl_solve_workspace_size exceeds 128 MiB fail
+ * with GL_E_INVALID_ARG before any launch (use gl_solve for them).  Every
+ * call on a GPU shares that GPU's array: calls that overlap on one GPU (two
+ * streams, two threads) race and give wrong results, so serialise them.
+ * Nothing in the array needs to start at zero (every call writes each part
+ * before it reads it); the array keeps the last call's contents.  Results
+ * are bitwise equal to gl_solve's for the same inputs (same kernels). */
+gl_status gl_solve_noalloc(const gl_operator *op, const gl_params *params, int32_t K,
+                           const int32_t *labels, gl_dtype store_u, void *U, double *stats,
+                           void *stream);
+
 /* Host-only check of a parameter block (the same checks gl_solve applies
  * before launching anything).  GL_OK or GL_E_INVALID_ARG with a message. */
 gl_status gl_params_validate(const gl_params *params);

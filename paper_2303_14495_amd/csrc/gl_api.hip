@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 
 #include <vector>
@@ -402,6 +403,45 @@ std::string bad_graph_message(int32_t flags, unsigned long long row) {
     if (flags & gl::BAD_ASYMMETRIC) m += " W not symmetric (pattern or weight);";
     if (flags & gl::BAD_DEGREE) m += " degree not finite and > 0;";
     return m;
+}
+
+}  // namespace
+
+namespace {
+
+// The solve behind gl_solve and gl_solve_noalloc (arguments as gl_solve).
+gl_status solve_impl(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
+                     gl_dtype store_u, void* U, void* ws, size_t ws_bytes, double* stats, void* stream);
+
+// Workspace of gl_solve_noalloc: a file-scope device array, one copy per GPU
+// the library's code is loaded on, held until the process ends.  Host code
+// never uses its name as an address: static_workspace() resolves the device
+// address once per device (hipGetSymbolAddress, with that device current)
+// and every launch takes that pointer.
+constexpr size_t kStaticWorkspaceBytes = (size_t)128 << 20;
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kStaticWorkspaceBytes];
+
+namespace {
+
+gl_status static_workspace(void** out) {
+    int dev = -1;
+    GL_HIP(hipGetDevice(&dev), "hipGetDevice");
+    if (dev < 0 || dev >= kMaxDevices) return fail(GL_E_INVALID_ARG, "device index beyond the static workspace table");
+    std::lock_guard<std::mutex> lock(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        GL_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)), "resolving the static workspace");
+        if (!ptr || !aligned(ptr, 256)) return fail(GL_E_HIP, "static workspace address is not 256-byte aligned");
+        g_scratch_ptr[dev] = ptr;
+    }
+    *out = g_scratch_ptr[dev];
+    return GL_OK;
 }
 
 }  // namespace
@@ -918,6 +958,35 @@ gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype sto
 
 gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
                    gl_dtype store_u, void* U, void* ws, size_t ws_bytes, double* stats, void* stream) {
+    return solve_impl(op, params, K, labels, store_u, U, ws, ws_bytes, stats, stream);
+}
+
+gl_status gl_solve_noalloc(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
+                           gl_dtype store_u, void* U, double* stats, void* stream) {
+    if (!gl::valid(op) || !labels || !U)
+        return fail(GL_E_INVALID_ARG, "operator (a live operator handle), labels and U must not be NULL");
+    if (K < 1 || K > 16) return fail(GL_E_INVALID_ARG, "K must lie in [1, 16]");
+    if (!pair_ok(op->store_w, store_u)) return fail(GL_E_DTYPE, "unsupported (weight, field) storage pair");
+    size_t need = 0;
+    const gl_status sz = gl_solve_workspace_size(op, K, store_u, &need);
+    if (sz != GL_OK) return sz;
+    if (need > kStaticWorkspaceBytes)
+        return fail(GL_E_INVALID_ARG, "this solve needs " + std::to_string(need) +
+                                          " bytes of workspace, more than the " +
+                                          std::to_string(kStaticWorkspaceBytes) +
+                                          "-byte static workspace of gl_solve_noalloc; use gl_solve");
+    void* ws = nullptr;
+    const gl_status st = static_workspace(&ws);
+    if (st != GL_OK) return st;
+    return solve_impl(op, params, K, labels, store_u, U, ws, kStaticWorkspaceBytes, stats, stream);
+}
+
+}  // extern "C"
+
+namespace {
+
+gl_status solve_impl(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
+                     gl_dtype store_u, void* U, void* ws, size_t ws_bytes, double* stats, void* stream) {
     if (!gl::valid(op) || !labels || !U || !ws) return fail(GL_E_INVALID_ARG, "operator (a live operator handle), labels, U and workspace must not be NULL");
     gl_status st = check_params(params);
     if (st != GL_OK) return st;
@@ -1036,6 +1105,10 @@ gl_status gl_solve(const gl_operator* op, const gl_params* params, int32_t K, co
         GL_HIP(copy_bytes(bufs[cur], U, (size_t)op->n * K * dtype_size(store_u), s), "result copy");
     return GL_OK;
 }
+
+}  // namespace
+
+extern "C" {
 
 gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t K, const int32_t* labels,
                          gl_dtype store_u, const void* U, void* ws, size_t ws_bytes, int32_t reps, double* avg_ms,

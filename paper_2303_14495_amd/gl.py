@@ -102,6 +102,7 @@ SIGNATURES = {
     "gl_solve_workspace_size": (ctypes.c_int, [_P, _I32, _I32, _P]),
     "gl_stats_length": (ctypes.c_int64, [_I32, _I32, _I32]),
     "gl_solve": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _P, _P, _SZ, _P, _P]),
+    "gl_solve_noalloc": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _P, _P, _P]),
     "gl_assign_labels": (ctypes.c_int, [_I64, _I32, _I32, _P, _P, _P]),
     "gl_params_validate": (ctypes.c_int, [_P]),
     "gl_time_sweeps": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _P, _P, _SZ, _I32, _P, _P]),
@@ -347,6 +348,20 @@ class Operator:
                             _ptr(ws), ws.numel(), _ptr(st) if st is not None else None,
                             _stream_handle(stream)))
         return st
+
+    def solve_noalloc(self, labels: torch.Tensor, U: torch.Tensor, stats_out: torch.Tensor | None,
+                      *, eps, c, eta, precond, outer, sweeps, delta0=1e-6, lambda_max=2.0,
+                      step_k=math.inf, stream=None):
+        """solve() through gl_solve_noalloc: the library's static workspace, no
+        allocation by the library or here (stats_out, if given, is the caller's
+        float64 [stats_length] device tensor)."""
+        if U.dim() != 2 or not U.is_contiguous() or labels.dtype != torch.int32 \
+                or not labels.is_contiguous():
+            raise ValueError("U must be contiguous n x K and labels contiguous int32")
+        p = _Params(eps, c, eta, delta0, lambda_max, step_k, PRECONDS[precond], outer, sweeps, 0)
+        _check(load_library().gl_solve_noalloc(
+            self._h, ctypes.byref(p), U.shape[1], _ptr(labels), DTYPES[DTYPE_OF_TORCH[U.dtype]],
+            _ptr(U), _ptr(stats_out) if stats_out is not None else None, _stream_handle(stream)))
 
 
 def time_sweeps(op: Operator, labels: torch.Tensor, U: torch.Tensor, *, eps, c, eta, precond,

@@ -1,0 +1,127 @@
+"""gl_solve_noalloc (the static-workspace variant of gl_solve) against gl_solve
+through the C ABI: bitwise equal fields and statistics on consecutive calls
+whose inputs shrink, so each call reuses what the previous one left in the
+shared array; and the size limit, rejected on the host before any launch."""
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2303_14495_amd as gl
+
+from .gpu_helpers import DEV, make_operator, problem, say
+
+pytestmark = pytest.mark.gpu
+
+STATIC_BYTES = 128 << 20
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _need_gpu():
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+
+
+def _both(p, op, store_u):
+    """(U, stats) of gl_solve and of gl_solve_noalloc on the same inputs."""
+    kw = dict(eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=p.outer, sweeps=p.sweeps,
+              delta0=p.delta0, lambda_max=2.0, step_k=p.step_k)
+    lab = torch.from_numpy(np.ascontiguousarray(p.labels, dtype=np.int32)).to(DEV)
+    U0 = torch.from_numpy(np.ascontiguousarray(p.u0)).to(DEV, gl.TORCH_DTYPES[store_u]).contiguous()
+    Ua = U0.clone()
+    st_a = op.solve(lab, Ua, **kw)
+    Ub = U0.clone()
+    st_b = torch.full_like(st_a, float("nan"))
+    op.solve_noalloc(lab, Ub, st_b, **kw)
+    torch.cuda.synchronize()
+    return Ua, st_a, Ub, st_b
+
+
+# largest first: every later call runs on what an earlier, larger one left
+CASES = [
+    (4, "bf16", "f16", "grid"),     # 128 x 128 texture image, K = 4, grid layout
+    (3, "bf16", "bf16", "auto"),    # 3 000 points in R^784, K = 10, direct layout
+    (1, "f32", "f32", "auto"),      # 4 096 points, K = 1
+    (2, "f32", "f32", "tile"),      # 64 x 64 image in Z-order: renumbered operator
+]
+
+
+def test_noalloc_equals_solve_on_shrinking_inputs():
+    ops = {}
+    prev_need = None
+    for cfg, sw, su, layout in CASES:
+        small = cfg != 1
+        p = problem(cfg, small=small)
+        say(f"noalloc vs gl_solve: workload {cfg} small={small} {sw}/{su} {layout} n={p.n} K={p.K}")
+        op = make_operator(p, sw, layout=layout)
+        ops[cfg] = op
+        need = op.workspace_bytes(p.K, su)
+        assert need <= STATIC_BYTES
+        Ua, st_a, Ub, st_b = _both(p, op, su)
+        assert torch.equal(Ua, Ub), "field differs from gl_solve"
+        assert torch.equal(st_a, st_b), "statistics differ from gl_solve"
+        assert float(st_b[-1]) == 0.0
+        prev_need = need
+    assert prev_need is not None
+
+
+def test_noalloc_repeated_call_same_result():
+    # the same solve twice in a row: the second starts from the first one's
+    # leftovers in the array and must not depend on them
+    p = problem(1)
+    op = make_operator(p, "f32")
+    kw = dict(eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=p.outer, sweeps=p.sweeps)
+    lab = torch.from_numpy(np.ascontiguousarray(p.labels, dtype=np.int32)).to(DEV)
+    outs = []
+    for _ in range(2):
+        U = torch.from_numpy(p.u0).to(DEV, torch.float32).contiguous()
+        st = torch.empty(gl.stats_length(1, p.outer, p.sweeps), dtype=torch.float64, device=DEV)
+        op.solve_noalloc(lab, U, st, **kw)
+        outs.append((U.clone(), st.clone()))
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0][0], outs[1][0]) and torch.equal(outs[0][1], outs[1][1])
+
+
+def test_noalloc_without_stats():
+    p = problem(1)
+    op = make_operator(p, "f32")
+    kw = dict(eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=p.outer, sweeps=p.sweeps)
+    lab = torch.from_numpy(np.ascontiguousarray(p.labels, dtype=np.int32)).to(DEV)
+    Ua = torch.from_numpy(p.u0).to(DEV, torch.float32).contiguous()
+    Ub = Ua.clone()
+    op.solve(lab, Ua, stats=False, **kw)
+    op.solve_noalloc(lab, Ub, None, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(Ua, Ub)
+
+
+def test_noalloc_rejects_solves_beyond_the_static_workspace():
+    # a cycle of 1.2 M nodes with K = 16 f32 columns needs two 76.8 MB field
+    # buffers: more than the array holds; rejected before any launch
+    n = 1_200_000
+    i = torch.arange(n, device=DEV, dtype=torch.int64)
+    nb = torch.stack([(i - 1) % n, (i + 1) % n], 1).sort(1).values
+    rp = torch.arange(0, 2 * n + 1, 2, device=DEV, dtype=torch.int64)
+    col = nb.reshape(-1).to(torch.int32).contiguous()
+    w = torch.ones(2 * n, dtype=torch.float64, device=DEV)
+    op = gl.Operator(rp, col, w, store_w="f32")
+    assert op.workspace_bytes(16, "f32") > STATIC_BYTES
+    lab = torch.full((n,), -1, dtype=torch.int32, device=DEV)
+    U = torch.zeros((n, 16), dtype=torch.float32, device=DEV)
+    U[:, 0] = 0.25
+    before = U.clone()
+    with pytest.raises(gl.GLError) as ei:
+        op.solve_noalloc(lab, U, None, eps=1.0, c=3.0, eta=0.0, precond="damped_jacobi",
+                         outer=1, sweeps=1)
+    assert ei.value.status == 1 and "static workspace" in ei.value.message
+    torch.cuda.synchronize()
+    assert torch.equal(U, before)
+    # K = 1 on the same operator fits and matches gl_solve
+    U1 = torch.full((n, 1), 0.25, dtype=torch.float32, device=DEV)
+    U1[::7] = -0.5
+    U2 = U1.clone()
+    kw = dict(eps=1.0, c=3.0, eta=0.0, precond="damped_jacobi", outer=2, sweeps=2)
+    op.solve(lab, U1, stats=False, **kw)
+    op.solve_noalloc(lab, U2, None, **kw)
+    torch.cuda.synchronize()
+    assert torch.equal(U1, U2)
