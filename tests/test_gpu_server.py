@@ -131,6 +131,32 @@ def test_mix_each_equals_alone():
         assert label_agreement(res["U"], Uo) >= 0.999
 
 
+# Requests of the served stream's sizes (N log-uniform in [1e4, 1e6]): the
+# direct geometry takes 2 and 4 row passes per block above about 1.6e4 rows
+# (block partial sums over several passes, blocks addressed from
+# block_begin), which the requests above do not reach.
+MIX_LARGE = [(20, 120000, 10, 12), (21, 20000, 4, 10), (22, 50000, 7, 16), (23, 3000, 3, 11)]
+
+
+def test_large_requests_multi_pass():
+    probs = [served(i, n, K, k) for (i, n, K, k) in MIX_LARGE]
+    srv = gl.Server(2 << 30, max_slots=4, store_w="bf16", store_u="bf16")
+    try:
+        tickets = [submit(srv, p) for p in probs]
+        results = [srv.poll(t) for t in tickets]
+        assert srv.info()["arena_used"] == 0
+    finally:
+        srv.close()
+    for (i, n, K, k), p, res in zip(MIX_LARGE, probs, results):
+        Uo = oracle(p)[0]
+        err = float(np.abs(res["U"] - Uo).max())
+        agree = label_agreement(res["U"], Uo)
+        say(f"  request {i}: n={n} nnz={p.graph.nnz} K={K} k={k}: max|U - oracle| {err:.3e}, "
+            f"labels {agree:.6f}")
+        assert_same_as_alone(res, alone(p, "bf16", "bf16"), f"request {i}")
+        assert err <= 2e-2 and agree >= 0.999
+
+
 def test_budget_serialises_admission():
     """An arena that holds one request at a time still serves all of them, in
     order, with the same results; a request above the budget is refused."""
