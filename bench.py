@@ -35,9 +35,9 @@ DSIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_sweep_image2048_k4_traffic.json")
 # sources whose change invalidates recorded counter traffic of the sweep kernel
 WINDOW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_sweep_1024_r12_traffic.json")  # + _<weights>
-TRAFFIC_SOURCES = ["gl_tile.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
-                   "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_f16.hip",
-                   "gl_unit_f32.hip", "gl_window.hpp", "gl_grid.hpp", "gl_api.hip"]
+TRAFFIC_SOURCES = ["gl_grid.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
+                   "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_grid_f16.hip",
+                   "gl_unit_grid_bf16.hip", "gl_unit_grid_f32.hip", "gl_window.hpp"]
 
 
 def sweep_source_hash():
@@ -73,6 +73,38 @@ def sweep_bytes(info, n, K, store_u):
     return info["stream_bytes"] + 3 * n * K * DSIZE[store_u] + 4 * n
 
 
+# index bytes stored per entry slot, by layout (padding slots carry them too)
+SLOT_INDEX_BYTES = {"grid": 1, "tile": 2, "direct": 4, "window": 0}
+
+
+def method_bytes(info, n, K, store_w, store_u):
+    """sweep_bytes without the layout's padding slots: what the graph's own
+    nonzeros, row data and the field cost per sweep."""
+    pad = info["stored_entries"] - info["nnz"]
+    return (sweep_bytes(info, n, K, store_u)
+            - pad * (SLOT_INDEX_BYTES[info["layout"]] + DSIZE[store_w]))
+
+
+def ceilings(dev, gib=4, reps=20):
+    """The practical HBM ceiling on this GPU: the library's plain read-only
+    streaming kernel and plain copy kernel over `gib` GiB (far beyond the
+    caches), mean time per launch over `reps` back-to-back launches."""
+    import torch
+    import paper_2303_14495_amd as gl
+    nb = gib << 30
+    buf = torch.empty(nb, dtype=torch.uint8, device=dev)
+    gl.time_stream(buf, "read", 3)
+    gl.time_stream(buf, "copy", 3)
+    read_ms = gl.time_stream(buf, "read", reps)
+    copy_ms = gl.time_stream(buf, "copy", reps)
+    del buf
+    torch.cuda.empty_cache()
+    return {"bytes": nb, "read_gbps": nb / (read_ms * 1e-3) / 1e9,
+            "copy_gbps": nb / (copy_ms * 1e-3) / 1e9,
+            "kernels": "stream_read_kernel (reads all bytes), stream_copy_kernel (reads half, "
+                       "writes half); 16-byte non-temporal vectors, 4096 x 256 lanes"}
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -95,6 +127,12 @@ def parse():
     ap.add_argument("--served-rates", default="",
                     help="comma-separated extra arrival rates, as multiples of the f32 capacity")
     ap.add_argument("--served-slots", type=int, default=32)
+    ap.add_argument("--no-hbm-scale", action="store_true",
+                    help="skip the 4096 x 4096 grid sweep (over 1 GB per sweep)")
+    ap.add_argument("--hbm-scale-only", action="store_true")
+    ap.add_argument("--no-precond", action="store_true",
+                    help="skip the preconditioner / step-size / Laplacian comparison")
+    ap.add_argument("--precond-only", action="store_true")
     ap.add_argument("--calib-copy", action="store_true",
                     help="finish with a 1 GiB device copy (counter calibration)")
     return ap.parse_args()
@@ -466,6 +504,137 @@ def knn_graph_bench(dev):
     return out
 
 
+def hbm_scale_bench(dev, reps):
+    """Workload 4's recipe on a 4096 x 4096 image (16.8 M pixels, about 370 M
+    stored nonzeros): the grid sweep at more than 1 GB per sweep, far beyond
+    the 256 MB Infinity Cache, with bf16/f16 and f32 storage; per form the
+    sweep time (back-to-back launches) and three timed solves."""
+    import numpy as np
+    import torch
+    import paper_2303_14495_amd as gl
+    from synth.configs import texture_problem
+    t0 = time.perf_counter()
+    p = texture_problem(4096, device=dev)
+    g = p.graph
+    torch.cuda.synchronize()
+    out = {"workload": p.name, "n": p.n, "nnz": g.nnz, "K": p.K, "outer_steps": p.outer,
+           "sweeps": p.sweeps, "graph_build_s": time.perf_counter() - t0}
+    log(f"  {p.name}: n={p.n} nnz={g.nnz} built in {out['graph_build_s']:.1f} s")
+    labels = torch.from_numpy(p.labels).to(dev)
+    x0 = torch.from_numpy(np.random.default_rng(10_000 + p.seed).uniform(-1, 1, p.n)).to(
+        dev, torch.float32)
+    for sw, su in (("bf16", "f16"), ("f32", "f32")):
+        torch.cuda.synchronize()
+        t1 = time.perf_counter()
+        op = gl.Operator(g.row_ptr, g.col, g.weight, store_w=sw, layout="grid",
+                         grid=p.extra["grid"])
+        torch.cuda.synchronize()
+        t_create = time.perf_counter() - t1
+        _, lam = op.power_max_eig(x0, 150)
+        U = torch.from_numpy(p.u0).to(dev, gl.TORCH_DTYPES[su]).contiguous()
+        sweep_ms = gl.time_sweeps(op, labels, U, eps=p.eps, c=p.c, eta=p.eta, precond=p.precond,
+                                  delta0=p.delta0, lambda_max=lam, step_k=p.step_k, reps=reps)
+        wall, _, _ = timed_solves(op, labels, U.clone(), p, lam, 3, 1)
+        info = op.info()
+        B = sweep_bytes(info, p.n, p.K, su)
+        Bm = method_bytes(info, p.n, p.K, sw, su)
+        out[f"{sw}/{su}"] = {
+            "kernel": f"grid_sweep_kernel<{p.K}, {sw}, {su}>", "sweep_kernel_ms": sweep_ms,
+            "sweep_bytes": B, "sweep_bytes_method": Bm,
+            "sweep_gbps": B / (sweep_ms * 1e-3) / 1e9,
+            "frac_of_hbm_peak": B / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "frac_method": Bm / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+            "solves_per_s": 3 / wall, "ms_per_solve": wall / 3 * 1e3,
+            "operator_create_ms": t_create * 1e3, "stored_entries": info["stored_entries"]}
+        log(f"  {sw}/{su}: {B / 1e9:.2f} GB per sweep in {sweep_ms * 1e3:.1f} us "
+            f"({out[f'{sw}/{su}']['sweep_gbps']:.0f} GB/s), {wall / 3 * 1e3:.1f} ms per solve")
+        op.close()
+        del U
+        torch.cuda.empty_cache()
+    del p, g, labels, x0
+    torch.cuda.empty_cache()
+    return out
+
+
+def precond_bench(dev, targets=(0.99, 0.995), max_steps=500):
+    """Synthetic analogs of the paper's preconditioner comparisons (Section
+    5.1.3, Tables 3-6) on its own image graph: the 1024 x 1024 rectangles
+    image, 25 x 25 window, 5 x 5 patches, eps = 100, c = 11, eta = 100, four
+    sweeps per DCA step, f32 storage, labels given as scribbles (a short stroke
+    through each rectangle and four in the background, as the paper's inputs
+    mark each object with a few strokes).  For each setting: the DCA steps (and
+    sweeps) until the labels first reach each accuracy target against the
+    synthetic ground truth (the paper stops on DICE against its ground truth),
+    and the time of one solve of that many steps.  Settings: L_s against L
+    with perturbed Jacobi (Table 3); damped Jacobi, perturbed Jacobi and
+    Richardson on L_s (Table 4); step sizes k = 0.01 ... 5 and infinity for
+    perturbed Jacobi and Richardson (Tables 5 and 6)."""
+    import numpy as np
+    import torch
+    import paper_2303_14495_amd as gl
+    from synth.configs import window_problem
+    p = window_problem(scribbles=True)
+    img = torch.from_numpy(p.image).to(dev, torch.float32)
+    labels = torch.from_numpy(p.labels).to(dev)
+    truth = torch.from_numpy(p.truth).to(dev)
+    U0 = torch.from_numpy(p.u0).to(dev, torch.float32).contiguous()
+    x0 = torch.from_numpy(np.random.default_rng(10_000 + p.seed).uniform(-1, 1, p.n)).to(
+        dev, torch.float32)
+    ops, lam = {}, {}
+    for lap in ("normalized", "unnormalized"):
+        ops[lap] = gl.Operator.window(img, p.rw, p.rp, p.sigma, store_w="f32", laplacian=lap)
+        lam[lap] = ops[lap].power_max_eig(x0, 150)[1]
+    base = dict(eps=p.eps, c=p.c, eta=p.eta, sweeps=p.sweeps, delta0=p.delta0, stats=False)
+
+    def run(lap, precond, k):
+        op = ops[lap]
+        kw = dict(base, precond=precond, lambda_max=lam[lap], step_k=k)
+        U = U0.clone()
+        first = {t: None for t in targets}
+        acc = 0.0
+        steps = 0
+        while steps < max_steps and first[targets[-1]] is None:
+            op.solve(labels, U, outer=1, **kw)
+            steps += 1
+            acc = float((gl.assign_labels(U) == truth).float().mean())
+            for t in targets:
+                if first[t] is None and acc >= t:
+                    first[t] = steps
+        # one solve of that many steps (bitwise the same iterates), timed alone
+        U = U0.clone()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        op.solve(labels, U, outer=steps, **kw)
+        torch.cuda.synchronize()
+        ms = (time.perf_counter() - t0) * 1e3
+        return {"laplacian": lap, "precond": precond, "step_k": "inf" if math.isinf(k) else k,
+                "steps_to": {str(t): first[t] for t in targets},
+                "sweeps_to": {str(t): (None if first[t] is None else first[t] * p.sweeps)
+                              for t in targets},
+                "steps_run": steps, "final_accuracy": acc, "ms": ms}
+
+    inf = math.inf
+    rows = []
+    seen = {}
+    plan = [("normalized", "perturbed_jacobi", inf), ("unnormalized", "perturbed_jacobi", inf),
+            ("normalized", "damped_jacobi", inf), ("normalized", "richardson", inf)]
+    plan += [("normalized", pc, k) for pc in ("perturbed_jacobi", "richardson")
+             for k in (0.01, 0.05, 0.1, 1.0, 5.0)]
+    for lap, pc, k in plan:
+        r = run(lap, pc, k)
+        seen[(lap, pc, k)] = r
+        rows.append(r)
+        log(f"  {lap:12s} {pc:16s} k={r['step_k']}: steps to {targets}: "
+            f"{[r['steps_to'][str(t)] for t in targets]}, {r['ms']:.1f} ms")
+    for op in ops.values():
+        op.close()
+    return {"workload": p.name, "n": p.n, "window": 2 * p.rw + 1, "storage": "f32/f32",
+            "labelled": int((p.labels >= 0).sum()),
+            "eps": p.eps, "c": p.c, "eta": p.eta, "sweeps_per_step": p.sweeps,
+            "accuracy_targets": list(targets), "max_steps": max_steps,
+            "lambda_hat": lam, "runs": rows}
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -482,6 +651,12 @@ def main():
     torch.cuda.set_device(dev)
     if args.window_only:
         print(json.dumps(window_bench(dev, args.steps, args.warmup, args.sweep_reps)), flush=True)
+        return
+    if args.precond_only:
+        print(json.dumps(precond_bench(dev)), flush=True)
+        return
+    if args.hbm_scale_only:
+        print(json.dumps(hbm_scale_bench(dev, args.sweep_reps)), flush=True)
         return
     if args.served_only:
         rates = [float(v) for v in args.served_rates.split(",") if v]
@@ -529,12 +704,14 @@ def main():
                                   step_k=p.step_k, reps=args.sweep_reps)
         info = op.info()
         B = sweep_bytes(info, p.n, p.K, store_u)
+        Bm = method_bytes(info, p.n, p.K, store_w, store_u)
         res = {
             "solves_per_s": steps / wall,
             "ms_per_solve": wall / steps * 1e3,
             "ms_per_solve_events": ev_ms / steps,
             "sweep_kernel_ms": sweep_ms,
             "sweep_bytes": B,
+            "sweep_bytes_method": Bm,
             "sweep_gbps": B / (sweep_ms * 1e-3) / 1e9,
             "operator_create_ms": t_create * 1e3,
             "power_method_ms": t_power * 1e3,
@@ -584,12 +761,32 @@ def main():
                 model = next((ln.split(":", 1)[1].strip() for ln in fh if ln.startswith("model name")), "")
         except OSError:
             pass
+        # the numpy/scipy oracle on one thread: the time of 4 more sweeps
+        # (runs of 1 and 5 sweeps in one DCA step, no energies)
+        from threadpoolctl import threadpool_limits
+        from oracle import gl_oracle
+        kw1 = dict(eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, delta0=p.delta0,
+                   lambda_max=lam_cpu, step_k=p.step_k, record=False)
+        log("CPU oracle sample, numpy/scipy on one thread: 1 and 5 sweeps")
+        with threadpool_limits(1):
+            ts = []
+            for m in (1, 5):
+                t1 = time.perf_counter()
+                gl_oracle.dca_solve(p.n, rp, col, w, p.labels, p.u0, outer=1, sweeps=m, **kw1)
+                ts.append(time.perf_counter() - t1)
+        s1 = max(ts[1] - ts[0], 1e-9) / 4
         cpu = {"value": solves / t_cpu, "unit": "solves/s",
                "cores": c_oracle.num_threads(), "kind": "oracle",
                "sample": (f"{solves} whole solves ({p.outer} DCA steps x {p.sweeps} sweeps + "
                           f"energies, float64, C+OpenMP) on the full graph, {t_cpu:.1f} s"),
                "s_per_sweep": t_cpu / (solves * p.outer * p.sweeps),  # energies included
-               "cpu_model": model, "host_cpus": os.cpu_count()}
+               "cpu_model": model, "host_cpus": os.cpu_count(),
+               "scipy_1core": {"s_per_sweep": s1, "cores": 1,
+                               "solves_per_s": 1.0 / (s1 * p.outer * p.sweeps),
+                               "sample": (f"numpy/scipy float64 oracle, one thread: one DCA step "
+                                          f"of 1 and of 5 sweeps on the full graph "
+                                          f"({ts[0]:.1f} s, {ts[1]:.1f} s); per sweep = "
+                                          f"difference / 4; solves/s excludes energies")}}
 
     log("unsupervised run (second eigenvector start)")
     unsup = unsupervised_bench(dev)
@@ -608,6 +805,18 @@ def main():
     kg = knn_graph_bench(dev)
     log(f"  {kg['points']} points: kNN {kg['knn_ms']:.1f} ms, graph {kg['graph_ms']:.1f} ms, "
         f"nnz {kg['nnz']}")
+
+    pcmp = None
+    if not args.no_precond:
+        log("preconditioners, step sizes and L against L_s on the window graph")
+        pcmp = precond_bench(dev)
+
+    ceil = ceilings(dev)
+    log(f"ceilings: read {ceil['read_gbps']:.0f} GB/s, copy {ceil['copy_gbps']:.0f} GB/s")
+    hbm = None
+    if not args.no_hbm_scale:
+        log("grid sweep beyond the caches (4096 x 4096 image)")
+        hbm = hbm_scale_bench(dev, args.sweep_reps)
 
     served = None
     if not args.no_served:
@@ -648,7 +857,19 @@ def main():
                      "kernel": {"tile": f"tile_sweep_kernel<{p.K}, {sw}, {su}>",
                                 "grid": f"grid_sweep_kernel<{p.K}, {sw}, {su}>"}.get(
                                     main_res["layout"], "sweep_kernel"),
-                     "bytes_per_launch": B},
+                     "bytes_per_launch": B,
+                     "bytes_per_launch_method": main_res["sweep_bytes_method"],
+                     "frac_method": main_res["sweep_bytes_method"]
+                     / (main_res["sweep_kernel_ms"] * 1e-3) / 1e9 / HBM_PEAK_GBPS,
+                     "measured_ceiling_gbps": ceil["read_gbps"],
+                     "frac_of_measured_ceiling": achieved / ceil["read_gbps"],
+                     "timing": ("mean per launch of --sweep-reps plain sweeps (the kernel "
+                                "named) back to back between one HIP event pair on their "
+                                "stream; sweep 0 of each DCA step and the energy-only pass "
+                                "run as grid_energy_sweep_kernel")},
+        "ceilings": ceil,
+        "hbm_scale": hbm,
+        "precond_comparison": pcmp,
         "cpu_baseline": cpu,
         "served": served,
         "unsupervised": unsup,

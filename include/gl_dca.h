@@ -362,6 +362,20 @@ gl_status gl_solve_noalloc(const gl_operator *op, const gl_params *params, int32
                            const int32_t *labels, gl_dtype store_u, void *U, double *stats,
                            void *stream);
 
+/* Measurement helper: the practical HBM ceiling that the sweep kernels are
+ * held against.  kind 0: a plain read-only streaming kernel reads all `bytes`
+ * of `buf` (16-byte non-temporal vector loads, four in flight per lane,
+ * grid-stride over 4096 workgroups of 256 lanes); kind 1: a plain copy kernel
+ * reads the first half of `buf` and writes the second half (bytes moved =
+ * `bytes`).  `reps` launches back to back between one pair of HIP events on
+ * `stream`; *avg_ms (host) receives the mean time per launch.
+ *   buf    device, 256-byte aligned, `bytes` long (contents: read, and for
+ *          kind 1 the second half overwritten); bytes a multiple of 256,
+ *          >= 1 MiB; use several GiB to measure HBM rather than the caches.
+ * Synchronises `stream`.  Errors: GL_E_INVALID_ARG, GL_E_HIP. */
+gl_status gl_time_stream(int32_t kind, void *buf, size_t bytes, int32_t reps, double *avg_ms,
+                         void *stream);
+
 /* Host-only check of a parameter block (the same checks gl_solve applies
  * before launching anything).  GL_OK or GL_E_INVALID_ARG with a message. */
 gl_status gl_params_validate(const gl_params *params);

@@ -15,6 +15,7 @@ from .gl import (  # noqa: F401
     load_library,
     split_stats,
     stats_length,
+    time_stream,
     time_sweeps,
     version,
     DTYPES,

@@ -17,7 +17,8 @@ CSRC = os.path.join(HERE, "csrc")
 BUILD = os.path.join(HERE, "_build")
 LIB = os.path.join(HERE, "libgl_dca.so")
 SOURCES = ["gl_api.hip", "gl_layout.hip", "gl_server.hip", "gl_knn.hip", "gl_eigen.hip", "gl_window.hip", "gl_graph.hip", "gl_knn_wide.hip", "gl_unit_f64.hip", "gl_unit_f32.hip",
-           "gl_unit_bf16.hip", "gl_unit_f16.hip"]
+           "gl_unit_bf16.hip", "gl_unit_f16.hip", "gl_unit_grid_f64.hip", "gl_unit_grid_f32.hip",
+           "gl_unit_grid_bf16.hip", "gl_unit_grid_f16.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 ARCH = "gfx950"
 FLAGS = ["-O3", "-std=c++17", "-fPIC", f"--offload-arch={ARCH}",

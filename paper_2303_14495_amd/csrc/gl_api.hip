@@ -12,11 +12,13 @@
 
 #include "gl_internal.hpp"
 #include "gl_kernels.hpp"
+#include "gl_direct.hpp"
 #include "gl_layout.hpp"
 #include "gl_sched.hpp"
 #include "gl_tile.hpp"
 #include "gl_window.hpp"
 #include "gl_grid.hpp"
+#include "gl_grid_build.hpp"
 
 
 namespace {
@@ -49,6 +51,8 @@ size_t dtype_size(int d) {
         default: return 0;
     }
 }
+
+typedef gl::u32x4 u32x4_alias;
 
 size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
 
@@ -113,6 +117,8 @@ gl::RowLaunch gl::operator_rows(const gl_operator* op) {
     r.log2G = op->log2G;
     r.tiles = op->tiles;
     r.remap = op->remap;
+    r.heavy = op->heavy;
+    r.nheavy = op->nheavy;
     r.rows_per_block = (int64_t)(gl::kBlock >> op->log2G) * op->tiles;
     r.grid = (op->n + r.rows_per_block - 1) / r.rows_per_block;
     return r;
@@ -278,6 +284,7 @@ void free_op(gl_operator* op) {
     (void)hipFree(op->goffs);
     (void)hipFree(op->gwbase);
     (void)hipFree(op->gcnt);
+    (void)hipFree(op->heavy);
     delete op;
 }
 
@@ -390,6 +397,22 @@ hipError_t upload(T** dst, const std::vector<T>& v, hipStream_t s) {
     hipError_t e = hipMalloc((void**)dst, bytes ? bytes : sizeof(T));
     if (e != hipSuccess) return e;
     if (bytes) e = hipMemcpyAsync(*dst, v.data(), bytes, hipMemcpyHostToDevice, s);
+    return e;
+}
+
+// The heavy rows of a direct-layout operator (rows longer than 16 G, summed by
+// workgroups of their own in the sweep), from host row offsets in the
+// operator's row order.
+template <typename OffT>
+hipError_t set_heavy_rows(gl_operator* op, const OffT* h_rp, hipStream_t s) {
+    const std::vector<int32_t> hv = gl::heavy_rows(op->n, h_rp, op->G);
+    if (hv.empty()) return hipSuccess;
+    hipError_t e = upload(&op->heavy, hv, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e == hipSuccess) {
+        op->nheavy = (int32_t)hv.size();
+        op->bytes += hv.size() * 4;
+    }
     return e;
 }
 
@@ -558,6 +581,96 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     if (init.flags) return cleanup_fail(GL_E_BAD_GRAPH, bad_graph_message(init.flags, init.first));
 
     const size_t sw = dtype_size(store_w);
+    if (grid_req) {
+        // grid layout, built on the device from the CSR graph and the degrees
+        const int32_t H = g->grid_height, W = g->grid_width;
+        const int32_t tiles_x = (W + gl::kGridTX - 1) / gl::kGridTX;
+        const int64_t ntiles = (int64_t)tiles_x * ((H + gl::kGridTY - 1) / gl::kGridTY);
+        const int64_t nseg = ntiles * gl::kGridTY;
+        op->layout = gl::LAYOUT_GRID;
+        op->idx64 = false;
+        op->G = 1;
+        op->wheight = H;
+        op->wwidth = W;
+        op->wtiles_x = tiles_x;
+        op->nblocks = ntiles;
+        int64_t* seg = nullptr;  // [nseg] rest chunks per segment, [nseg] their offsets, [1] total
+        struct {
+            int32_t flags, mincnt;
+            unsigned long long first;
+        } st = {0, 1 << 30, ~0ull};
+        int64_t rest = 0;
+        auto grid_fail = [&](gl_status code, const std::string& m) {
+            (void)hipStreamSynchronize(s);
+            (void)hipFree(seg);
+            return cleanup_fail(code, m);
+        };
+        if (hipMalloc((void**)&op->gcnt, (size_t)g->n) != hipSuccess ||
+            hipMalloc((void**)&op->gwbase, (size_t)H * tiles_x * 8) != hipSuccess ||
+            hipMalloc((void**)&seg, (size_t)(2 * nseg + 1) * 8) != hipSuccess)
+            return grid_fail(GL_E_NOMEM, "device allocation for the operator failed");
+        int32_t* d_st = (int32_t*)scratch;  // flags, mincnt, first bad pixel
+        if (hipMemcpyAsync(scratch, &st, sizeof(st), hipMemcpyHostToDevice, s) != hipSuccess)
+            return grid_fail(GL_E_HIP, "grid layout: copy failed");
+        hipLaunchKernelGGL(gl::grid_count_kernel, dim3(grid), dim3(256), 0, s, g->n, W, g->row_ptr, g->col_idx,
+                           op->gcnt, d_st, (unsigned long long*)((char*)scratch + 8), d_st + 1);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&st, scratch, sizeof(st), hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return grid_fail(GL_E_HIP, "grid layout: chunk counts failed");
+        if (st.flags)
+            return grid_fail(GL_E_INVALID_ARG, "grid layout: pixel " + std::to_string(st.first) +
+                                                   " has an edge more than 7 rows or columns away");
+        const int32_t dense = std::min(st.mincnt, gl::kGridDenseMax);
+        hipLaunchKernelGGL(gl::grid_segrest_kernel, dim3((unsigned)((nseg + 255) / 256)), dim3(256), 0, s, nseg, H,
+                           W, tiles_x, op->gcnt, dense, seg);
+        hipLaunchKernelGGL(gl::scan_exclusive_kernel, dim3(1), dim3(1024), 0, s, seg, seg + nseg, nseg,
+                           seg + 2 * nseg);
+        if (hipGetLastError() != hipSuccess ||
+            hipMemcpyAsync(&rest, seg + 2 * nseg, 8, hipMemcpyDeviceToHost, s) != hipSuccess ||
+            hipStreamSynchronize(s) != hipSuccess)
+            return grid_fail(GL_E_HIP, "grid layout: segment offsets failed");
+        const int64_t chunks = ntiles * dense * gl::kGridThreads + rest;
+        op->gchunks = chunks;
+        op->gdense = dense;
+        op->stored = chunks * gl::kGridChunk;
+        if (hipMalloc((void**)&op->goffs, (size_t)chunks * 8) != hipSuccess ||
+            hipMalloc(&op->w, (size_t)op->stored * sw + 64) != hipSuccess)
+            return grid_fail(GL_E_NOMEM, "device allocation for the operator failed");
+        op->bytes = (size_t)op->stored * sw + (size_t)chunks * 8 + (size_t)H * tiles_x * 8 + (size_t)g->n +
+                    (size_t)g->n * 8;
+        const int raw = op->lap == GL_LAP_UNNORMALIZED ? 1 : 0;
+        const dim3 eg((unsigned)((nseg + 3) / 4)), eb(256);
+        auto emit = [&](auto tin, auto tout) {
+            typedef decltype(tin) TIN;
+            typedef decltype(tout) TOUT;
+            hipLaunchKernelGGL((gl::grid_emit_kernel<TIN, TOUT>), eg, eb, 0, s, nseg, H, W, tiles_x, dense,
+                               g->row_ptr, g->col_idx, (const TIN*)g->weight, op->degree, raw, op->gcnt, seg + nseg,
+                               ntiles * dense * gl::kGridThreads, op->goffs, (TOUT*)op->w, op->gwbase);
+        };
+        auto emit_in = [&](auto tin) {
+            switch (store_w) {
+                case GL_F64: emit(tin, double{}); break;
+                case GL_F32: emit(tin, float{}); break;
+                case GL_BF16: emit(tin, gl::bf16{}); break;
+                default: emit(tin, gl::f16{}); break;
+            }
+        };
+        if (g->weight_dtype == GL_F64) emit_in(double{});
+        else emit_in(float{});
+        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
+            return grid_fail(GL_E_HIP, "grid layout: chunk emission failed");
+        (void)hipFree(seg);
+        seg = nullptr;
+        const gl_status su = finish_unnormalized(op, s, g);
+        if (su != GL_OK) {
+            const std::string m = gl_last_error();
+            return cleanup_fail(su, m);
+        }
+        (void)hipFree(scratch);
+        *out = op;
+        return GL_OK;
+    }
     if (!host_layout) {
         // direct layout in natural order, built on the device
         const size_t rp_bytes = (size_t)(g->n + 1) * (op->idx64 ? 8 : 4);
@@ -569,6 +682,12 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         else launch_normalize_out<float>(op, g, s);
         if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
             return cleanup_fail(GL_E_HIP, "weight normalization failed");
+        {
+            std::vector<int64_t> h_rp(g->n + 1);
+            if (hipMemcpy(h_rp.data(), g->row_ptr, h_rp.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
+                set_heavy_rows(op, h_rp.data(), s) != hipSuccess)
+                return cleanup_fail(GL_E_HIP, "heavy-row list failed");
+        }
         const gl_status su = finish_unnormalized(op, s);
         if (su != GL_OK) {
             const std::string m = gl_last_error();
@@ -597,66 +716,6 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
                                                           std::to_string(p) + ")");
             seen[i] = 1;
         }
-    }
-    if (grid_req) {
-        gl::GridLayout GLy;
-        std::string gerr;
-        if (!gl::build_grid_layout(g->n, g->grid_height, g->grid_width, h_rp.data(), h_col.data(), GLy, gerr))
-            return cleanup_fail(GL_E_INVALID_ARG, gerr);
-        h_col.clear();
-        h_col.shrink_to_fit();
-        op->layout = gl::LAYOUT_GRID;
-        op->idx64 = false;
-        op->G = 1;
-        op->wheight = g->grid_height;
-        op->wwidth = g->grid_width;
-        op->wtiles_x = GLy.tiles_x;
-        op->nblocks = (int64_t)GLy.tiles_x * ((g->grid_height + gl::kGridTY - 1) / gl::kGridTY);
-        op->gchunks = GLy.chunks;
-        op->gdense = GLy.dense;
-        op->stored = GLy.chunks * gl::kGridChunk;
-        hipError_t e = upload(&d_src, GLy.src, s);
-        std::vector<uint64_t> offs64((size_t)GLy.chunks);
-        if (GLy.chunks) std::memcpy(offs64.data(), GLy.offs.data(), (size_t)GLy.chunks * 8);
-        GLy.offs.clear();
-        GLy.offs.shrink_to_fit();
-        if (e == hipSuccess) e = upload(&op->goffs, offs64, s);
-        if (e == hipSuccess) e = upload(&op->gwbase, GLy.wbase, s);
-        if (e == hipSuccess) e = upload(&op->gcnt, GLy.cnt, s);
-        if (e == hipSuccess) e = hipMalloc(&op->w, (size_t)op->stored * sw + 64);
-        if (e == hipSuccess) e = hipStreamSynchronize(s);
-        if (e != hipSuccess) return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
-        op->bytes = (size_t)op->stored * sw + (size_t)GLy.chunks * 8 + GLy.wbase.size() * 8 + (size_t)g->n +
-                    (size_t)g->n * 8;
-        const unsigned gs = (unsigned)((op->stored + 255) / 256);
-        const int raw = op->lap == GL_LAP_UNNORMALIZED ? 1 : 0;
-        auto fill = [&](auto tin, auto tout) {
-            typedef decltype(tin) TIN;
-            typedef decltype(tout) TOUT;
-            hipLaunchKernelGGL((gl::grid_fill_kernel<TIN, TOUT>), dim3(gs), dim3(256), 0, s, op->stored, g->n,
-                               g->row_ptr, g->col_idx, (const TIN*)g->weight, op->degree, d_src, (TOUT*)op->w, raw);
-        };
-        auto fill_in = [&](auto tin) {
-            switch (store_w) {
-                case GL_F64: fill(tin, double{}); break;
-                case GL_F32: fill(tin, float{}); break;
-                case GL_BF16: fill(tin, gl::bf16{}); break;
-                default: fill(tin, gl::f16{}); break;
-            }
-        };
-        if (g->weight_dtype == GL_F64) fill_in(double{});
-        else fill_in(float{});
-        if (hipGetLastError() != hipSuccess || hipStreamSynchronize(s) != hipSuccess)
-            return cleanup_fail(GL_E_HIP, "weight normalization failed");
-        const gl_status su = finish_unnormalized(op, s, g);
-        if (su != GL_OK) {
-            const std::string m = gl_last_error();
-            return cleanup_fail(su, m);
-        }
-        (void)hipFree(d_src);
-        (void)hipFree(scratch);
-        *out = op;
-        return GL_OK;
     }
     gl::HostLayout L;
     std::string err;
@@ -704,6 +763,8 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
     const bool fill_ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
     (void)hipFree(d_pos_of);
     if (!fill_ok) return cleanup_fail(GL_E_HIP, "weight normalization failed");
+    if (op->layout == gl::LAYOUT_DIRECT && set_heavy_rows(op, L.rp.data(), s) != hipSuccess)
+        return cleanup_fail(GL_E_HIP, "heavy-row list failed");
     const gl_status su = finish_unnormalized(op, s);
     if (su != GL_OK) {
         const std::string m = gl_last_error();
@@ -952,7 +1013,7 @@ gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype sto
     // ordered operators keep all three field buffers and the labels in position order
     // the block partial sums of up to kStatGroup sweeps wait for one reduction
     *bytes = (op->order ? 3 * field + align256((size_t)op->n * 4) : 2 * field) +
-             (size_t)gl::kStatGroup * align256((size_t)2 * K * r.grid * acc);
+             (size_t)gl::kStatGroup * align256((size_t)2 * K * gl::sweep_grid(r) * acc);
     return GL_OK;
 }
 
@@ -1039,7 +1100,7 @@ gl_status solve_impl(const gl_operator* op, const gl_params* params, int32_t K, 
     // The statistics of each sweep are reduced later, kStatGroup sweeps per
     // launch: sweep j of a group writes its block partial sums to set j.
     const size_t acc = store_u == GL_F64 ? 8 : 4;
-    const size_t set_bytes = align256((size_t)2 * K * L.r.grid * acc);
+    const size_t set_bytes = align256((size_t)2 * K * gl::sweep_grid(L.r) * acc);
     gl::StatGroup group = {};
     int pending = 0;
     auto flush = [&]() -> hipError_t {
@@ -1048,10 +1109,10 @@ gl_status solve_impl(const gl_operator* op, const gl_params* params, int32_t K, 
         const int64_t stride = (int64_t)(set_bytes / acc);
         if (store_u == GL_F64) {
             hipLaunchKernelGGL(gl::finalize_group_kernel<double>, grid, dim3(256), 0, s,
-                               (const double*)partials, L.r.grid, stride, K, group, flag);
+                               (const double*)partials, gl::sweep_grid(L.r), stride, K, group, flag);
         } else {
             hipLaunchKernelGGL(gl::finalize_group_kernel<float>, grid, dim3(256), 0, s,
-                               (const float*)partials, L.r.grid, stride, K, group, flag);
+                               (const float*)partials, gl::sweep_grid(L.r), stride, K, group, flag);
         }
         pending = 0;
         group = {};
@@ -1176,6 +1237,41 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     GL_HIP(err, "timed sweeps");
     const double ms = total;
     *avg_ms = (double)ms / reps;
+    return GL_OK;
+}
+
+gl_status gl_time_stream(int32_t kind, void* buf, size_t bytes, int32_t reps, double* avg_ms, void* stream) {
+    if (!buf || !avg_ms) return fail(GL_E_INVALID_ARG, "buf and avg_ms must not be NULL");
+    if (kind != 0 && kind != 1) return fail(GL_E_INVALID_ARG, "kind must be 0 (read) or 1 (copy)");
+    if (reps < 1 || reps > 10000) return fail(GL_E_INVALID_ARG, "reps must lie in [1, 10000]");
+    if (!aligned(buf, 256)) return fail(GL_E_INVALID_ARG, "buf must be 256-byte aligned");
+    if (bytes < ((size_t)1 << 20) || bytes % 256) return fail(GL_E_INVALID_ARG, "bytes must be a multiple of 256, >= 1 MiB");
+    hipStream_t s = (hipStream_t)stream;
+    const int64_t n16 = (int64_t)(kind == 0 ? bytes : bytes / 2) / 16;
+    const u32x4_alias* src = (const u32x4_alias*)buf;
+    u32x4_alias* dst = (u32x4_alias*)((char*)buf + bytes / 2);
+    // 16 workgroups of 256 lanes per compute unit
+    const dim3 grid(4096), block(256);
+    hipEvent_t ev[2] = {nullptr, nullptr};
+    hipError_t err = hipEventCreate(&ev[0]);
+    if (err == hipSuccess) err = hipEventCreate(&ev[1]);
+    if (err == hipSuccess) err = hipEventRecord(ev[0], s);
+    for (int i = 0; i < reps && err == hipSuccess; ++i) {
+        if (kind == 0)
+            hipLaunchKernelGGL(gl::stream_read_kernel, grid, block, 0, s, src, n16, 0x9e3779b9u,
+                               (u32x4_alias*)buf);
+        else
+            hipLaunchKernelGGL(gl::stream_copy_kernel, grid, block, 0, s, src, dst, n16);
+        err = hipGetLastError();
+    }
+    if (err == hipSuccess) err = hipEventRecord(ev[1], s);
+    if (err == hipSuccess) err = hipEventSynchronize(ev[1]);
+    float total = 0.f;
+    if (err == hipSuccess) err = hipEventElapsedTime(&total, ev[0], ev[1]);
+    for (hipEvent_t e : ev)
+        if (e) (void)hipEventDestroy(e);
+    GL_HIP(err, "timed streaming");
+    *avg_ms = (double)total / reps;
     return GL_OK;
 }
 

@@ -7,14 +7,9 @@
 // diagonal update v + r/g (Section 3.1) and the block partial sums of |r|^2 and of
 // the energy terms (Section 2.1).
 //
-// Work mapping (CDNA4, 64-lane wavefronts): a group of G lanes (G a power of two,
-// 4..64, chosen from the mean row length) owns one CSR row.  Lane q of the group
-// streams nonzeros q, q+G, q+2G, ... so one load instruction of the wavefront reads
-// 64/G consecutive rows' index and weight runs; each nonzero gathers the whole
-// K-wide row of V with one or a few vector loads.  The G partial sums are combined
-// by a butterfly of cross-lane swaps, which leaves the same bits in every lane of
-// the group; lane q then finishes columns q, q+G, ...  Every sum has a fixed order,
-// independent of K and of the launch, so results are bitwise reproducible.
+// The row kernels of each operator layout (direct CSR, tile, grid, window) are
+// in their own headers; this one holds the storage types, row loads and stores
+// and the fixed-order wavefront and block reductions they share.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -220,43 +215,6 @@ template <typename A> __device__ __forceinline__ A xor_add(A x, int off) {
     if (off == 1) return dpp_add<0xb1, 0xf>(x);
     if (off == 2) return dpp_add<0x4e, 0xf>(x);
     return x + __shfl_xor(x, off, 64);
-}
-
-// z = sum_j what_ij V[j, :] for `row`, completed in every lane of its G-lane group.
-// Rows >= n contribute zeros but still take part in the cross-lane swaps.
-template <int K, typename TW, typename TU, typename OffT, typename A>
-__device__ __forceinline__ void row_gather(const OffT* __restrict__ rp, const int32_t* __restrict__ col,
-                                           const TW* __restrict__ w, const TU* __restrict__ V,
-                                           int64_t row, int64_t n, int q, int G, A (&z)[K]) {
-#pragma unroll
-    for (int k = 0; k < K; ++k) z[k] = (A)0;
-    if (row < n) {
-        const OffT beg = rp[row], end = rp[row + 1];
-        OffT p = beg + (OffT)q;
-        for (; p + (OffT)G < end; p += (OffT)(2 * G)) {
-            const int32_t j0 = col[p], j1 = col[p + G];
-            const A w0 = cvt<A>(w[p]), w1 = cvt<A>(w[p + G]);
-            A v0[K], v1[K];
-            load_row<K>(V + (int64_t)j0 * K, v0);
-            load_row<K>(V + (int64_t)j1 * K, v1);
-#pragma unroll
-            for (int k = 0; k < K; ++k) z[k] += w0 * v0[k];
-#pragma unroll
-            for (int k = 0; k < K; ++k) z[k] += w1 * v1[k];
-        }
-        if (p < end) {
-            const int32_t j0 = col[p];
-            const A w0 = cvt<A>(w[p]);
-            A v0[K];
-            load_row<K>(V + (int64_t)j0 * K, v0);
-#pragma unroll
-            for (int k = 0; k < K; ++k) z[k] += w0 * v0[k];
-        }
-    }
-    for (int off = G >> 1; off > 0; off >>= 1) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) z[k] += __shfl_xor(z[k], off, 64);
-    }
 }
 
 // Sum the per-lane column partials of a 256-thread block.  Lane q of every group

@@ -11,13 +11,15 @@
 // K values per cell side by side (one vector LDS read per entry), zeros
 // outside the image.  Chunks are stored so that every wavefront load is
 // contiguous.  The first `dense` chunks of every pixel (dense = the smallest
-// chunk count of the graph, at most 4) are stored by pixel, chunk r of pixel
-// p at r * n + p, so a lane can request them before it knows its chunk count.
-// The others follow by row segment: within a wavefront (a 64-pixel row
-// segment), chunk c of all lanes that have more than c chunks follows chunk
-// c - 1 of all lanes, in lane order; a lane finds its chunk from the
-// segment's first chunk, a ballot of the lanes still active and a population
-// count.  A sweep thus
+// chunk count of the graph, at most 4) are stored tile by tile, chunk r of lane
+// l of tile t at (t * dense + r) * 512 + l, so a lane can request them before it
+// knows its chunk count and a workgroup reads them as `dense` contiguous spans
+// (long DRAM bursts, as for a plain stream).  The others follow by row
+// segment, the segments of a tile one after another: within a wavefront (a
+// 64-pixel row segment), chunk c of all lanes that have more than c chunks
+// follows chunk c - 1 of all lanes, in lane order; a lane finds its chunk from
+// the segment's first chunk, a ballot of the lanes still active and a
+// population count.  A sweep thus
 // streams 3 bytes per entry in BF16/F16 (1 + 2), plus padding, and no row
 // offsets or halo lists.
 #pragma once
@@ -44,7 +46,7 @@ struct GridOp {
     const int64_t* wbase;   // [height * tiles_x] first chunk of each wavefront
     const uint8_t* cnt;     // [n] chunks per pixel
     int64_t n;              // pixels
-    int32_t dense;          // chunk rounds stored by pixel (<= kGridGroup): chunk r of pixel p is r * n + p
+    int32_t dense;          // chunk rounds stored by tile (<= kGridGroup): chunk r of lane l of tile t is (t dense + r) 512 + l
     int32_t height, width, tiles_x;
 };
 
@@ -156,7 +158,7 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
 #pragma unroll
     for (int u = 0; u < U; ++u) {
         if (u < op.dense && ok) {
-            const int64_t id = (int64_t)u * op.n + p;
+            const int64_t id = ((int64_t)bi * op.dense + u) * kGridThreads + (int)threadIdx.x;
             // streamed once per sweep: keep the staged V halos of other tiles in L2
             ob[u] = __builtin_nontemporal_load(op.offs + id);
 #pragma unroll
@@ -302,9 +304,12 @@ template <typename TU, typename A> struct GridSweepArgs {
 };
 
 // One sweep (or the energy-only pass) on the grid layout; the update is the
-// one of sweep_block, for all K columns of the lane's pixel.
-template <int K, typename TW, typename TU>
-__global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<TU, typename acc_of<TU>::type> a) {
+// one of sweep_block, for all K columns of the lane's pixel.  EN: the energy
+// terms are accumulated (a.energy is ignored); two kernel names below, so the
+// sweeps that carry the energy reduction (sweep 0 of every DCA step and the
+// energy-only pass) are timed apart from the plain sweeps.
+template <int K, typename TW, typename TU, bool EN>
+__device__ __forceinline__ void grid_sweep_body(const GridSweepArgs<TU, typename acc_of<TU>::type>& a) {
     typedef typename acc_of<TU>::type A;
     extern __shared__ unsigned char smem_raw[];
     void* hv = smem_raw;
@@ -335,16 +340,29 @@ __global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<
             const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
             vnew[k] = store_as<TU>::from(v + r * ginv);
             r_acc[k] += r * r;
-            if (a.energy) {
+            if constexpr (EN) {
                 const A u2m1 = u * u - (A)1, dy = u - y;
                 const A ulu = fma_acc(u, a.dd ? dl * u : u, -(u * zk));  // u (L u)_i, one rounding
                 e_acc[k] += a.k.half_eps * ulu + a.k.quarter_inv_eps * u2m1 * u2m1 + a.k.half_eta * lam * dy * dy;
             }
         }
-        if (a.vout) store_raw<K>(a.vout + p * K, vnew);
+        if (!EN || a.vout) store_raw<K>(a.vout + p * K, vnew);
     };
     grid_products<K, TW, TU, A>(a.op, a.vin, b, hv, prefetch, finish);
-    if (a.partials) block_stats_lanes<K, kGridTY>(e_acc, r_acc, a.partials, (int64_t)gridDim.x, b, a.energy != 0);
+    if (a.partials) block_stats_lanes<K, kGridTY>(e_acc, r_acc, a.partials, (int64_t)gridDim.x, b, EN);
+}
+
+// A plain sweep: no energy terms, always stores the new field.
+template <int K, typename TW, typename TU>
+__global__ __launch_bounds__(kGridThreads) void grid_sweep_kernel(GridSweepArgs<TU, typename acc_of<TU>::type> a) {
+    grid_sweep_body<K, TW, TU, false>(a);
+}
+
+// Sweep 0 of a DCA step with the energy terms of u^t, or (vout == nullptr) the
+// energy-only pass after the last step.
+template <int K, typename TW, typename TU>
+__global__ __launch_bounds__(kGridThreads) void grid_energy_sweep_kernel(GridSweepArgs<TU, typename acc_of<TU>::type> a) {
+    grid_sweep_body<K, TW, TU, true>(a);
 }
 
 // Y = X - What X (L_s X) or D X - W X (L X) on the grid layout
@@ -410,30 +428,6 @@ __global__ __launch_bounds__(kGridThreads) void grid_power_kernel(GridPowerArgs 
     grid_products<1, TW, float, float>(a.op, a.x, b, hv, prefetch, finish);
     float e[1] = {p0}, r[1] = {p1};
     block_stats_lanes<1, kGridTY>(e, r, a.partials, (int64_t)gridDim.x, b);
-}
-
-// Grid layout weights: slot s takes the weight of CSR entry src[s]
-// (w / (sqrt(d_i) sqrt(d_j)) for L_s, w itself for L, rounded once), or 0 for
-// padding (src[s] < 0).  The row i of an entry is found by binary search.
-template <typename TIN, typename TOUT>
-__global__ void grid_fill_kernel(int64_t slots, int64_t n, const int64_t* __restrict__ rp,
-                                 const int32_t* __restrict__ col, const TIN* __restrict__ w,
-                                 const double* __restrict__ d, const int32_t* __restrict__ src,
-                                 TOUT* __restrict__ w_out, int32_t raw) {
-    const int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-    if (s >= slots) return;
-    const int32_t e = src[s];
-    if (e < 0) {
-        w_out[s] = store_as<TOUT>::from(0.0);
-        return;
-    }
-    int64_t lo = 0, hi = n;  // last row with rp[row] <= e
-    while (hi - lo > 1) {
-        const int64_t mid = (lo + hi) >> 1;
-        if (rp[mid] <= e) lo = mid; else hi = mid;
-    }
-    const double wv = (double)w[e];
-    w_out[s] = store_as<TOUT>::from(raw ? wv : wv / (sqrt(d[lo]) * sqrt(d[col[e]])));
 }
 
 // Unnormalized L on the grid layout: dd_i = sum over row i of the weights as

@@ -28,6 +28,8 @@ struct RowLaunch {
     bool idx64;
     int64_t rows_per_block;
     int32_t G, log2G, tiles, remap;
+    const int32_t* heavy;  // rows longer than 16 G (summed by workgroups of their own in the sweep)
+    int32_t nheavy;
     // tile layout
     const int32_t* trp;
     const uint16_t* lcol;
@@ -83,6 +85,8 @@ struct gl_operator {
     void* dd = nullptr;   // unnormalized L: diagonal d (accumulator type, position order)
     double dmax = 1.0;    // largest diagonal entry of the Laplacian (1 for L_s)
     int32_t G = 16, log2G = 4, tiles = 4, remap = 1;
+    int32_t* heavy = nullptr;  // direct layout: rows longer than 16 G, in position order
+    int32_t nheavy = 0;
     // window layout: image height x width, window radius, offsets per pixel,
     // tiles per image row, LDS offset of every window offset
     int32_t wheight = 0, wwidth = 0, wr = 0, wM = 0, wtiles_x = 0;
@@ -107,6 +111,13 @@ inline bool valid(const gl_operator* op) { return op != nullptr && op->magic == 
 // Row-kernel launch description of an operator.
 RowLaunch operator_rows(const gl_operator* op);
 
+// Workgroups of one sweep launch: the row blocks, and on the direct layout the
+// heavy rows' workgroups (a multiple of 8) before them.  The sweep's block
+// partial sums have one slot per workgroup.
+inline int64_t sweep_grid(const RowLaunch& r) {
+    return r.grid + (r.layout == LAYOUT_DIRECT ? ((int64_t)r.nheavy + 7) / 8 * 8 : 0);
+}
+
 // Power-method pass on the window layout (see gl::window_power_kernel).
 hipError_t launch_window_power(const gl_operator* op, const float* x, float* y, int mode, const float* scale,
                                float* partials, hipStream_t s);
@@ -128,6 +139,12 @@ hipError_t launch_sweep_f64(int K, const SweepLaunch& L, hipStream_t s);
 hipError_t launch_sweep_f32(int K, const SweepLaunch& L, hipStream_t s);
 hipError_t launch_sweep_bf16(int K, const SweepLaunch& L, hipStream_t s);
 hipError_t launch_sweep_f16(int K, const SweepLaunch& L, hipStream_t s);
+
+// Grid-layout sweeps (their own compile units), dispatched by launch_sweep_*.
+hipError_t launch_grid_sweep_f64(int K, const SweepLaunch& L, hipStream_t s);
+hipError_t launch_grid_sweep_f32(int K, const SweepLaunch& L, hipStream_t s);
+hipError_t launch_grid_sweep_bf16(int K, const SweepLaunch& L, hipStream_t s);
+hipError_t launch_grid_sweep_f16(int K, const SweepLaunch& L, hipStream_t s);
 
 hipError_t launch_laplacian_f64(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s);
 hipError_t launch_laplacian_f32(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s);

@@ -43,158 +43,10 @@ template <typename TW, typename TU, typename OffT> struct SweepArgs {
     RowGeom g;
     int32_t energy;    // also accumulate the energy terms (vin == ut)
     SweepCoef<A> k;
+    const int32_t* heavy;  // direct layout: rows longer than 16 G, summed by workgroups of their own
+    int32_t nheavy;        // number of heavy rows
+    int32_t hblocks;       // their workgroups (nheavy rounded up to a multiple of 8), first in the launch
 };
-
-// One sweep (or the energy-only pass) over logical block b of nb blocks.
-template <int K, typename TW, typename TU, typename OffT>
-__device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, int64_t b, int64_t nb) {
-    typedef typename acc_of<TU>::type A;
-    constexpr int CPL = (K + 3) / 4;  // columns per lane (G >= 4)
-    const int G = a.g.G;
-    const int q = threadIdx.x & (G - 1);
-    const int grp = threadIdx.x >> a.g.log2G;
-    const int rows_per_tile = kBlock >> a.g.log2G;
-    const int64_t row0 = b * a.g.rows_per_block;
-    A e_acc[CPL], r_acc[CPL];
-#pragma unroll
-    for (int c = 0; c < CPL; ++c) e_acc[c] = r_acc[c] = (A)0;
-
-    for (int t = 0; t < a.g.tiles; ++t) {
-        const int64_t row = row0 + (int64_t)t * rows_per_tile + grp;
-        A z[K];
-        row_gather<K>(a.rp, a.col, a.w, a.vin, row, a.g.n, q, G, z);
-        if (row < a.g.n) {
-            const int64_t node = a.order ? (int64_t)a.order[row] : row;
-            const int32_t lab = a.labels[node];
-            const A lam = lab >= 0 ? (A)1 : (A)0;
-            const A dl = a.dd ? a.dd[node] : (A)1;
-            const A ginv = a.dd ? (A)1 / (a.k.ga + a.k.gd * dl + a.k.gl * lam)
-                                : (lab >= 0 ? a.k.ginv1 : a.k.ginv0);
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int k = q + c * G;
-                if (k < K) {
-                    const A zk = pick<K>(z, k);
-                    const int64_t at = node * K + k;
-                    const A u = cvt<A>(a.ut[at]);
-                    const A v = cvt<A>(a.vin[at]);
-                    const A y = lab < 0 ? (A)0
-                              : (K == 1 ? (lab == 1 ? (A)1 : (A)-1) : (lab == k ? (A)1 : (A)-1));
-                    const A rhs = a.k.c * u - (u * u * u - u) * a.k.inv_eps + a.k.eta * lam * y;
-                    const A lv = a.dd ? dl * v - zk : v - zk;  // (L v)_i or (L_s v)_i
-                    const A tv = a.k.eps * lv + (a.k.eta * lam + a.k.c) * v;
-                    const A r = a.k.alpha * (u - v) + a.k.kappa * (rhs - tv);
-                    if (a.vout) a.vout[at] = store_as<TU>::from(v + r * ginv);
-                    r_acc[c] += r * r;
-                    if (a.energy) {
-                        const A u2m1 = u * u - (A)1, dy = u - y;
-                        const A ulu = fma_acc(u, a.dd ? dl * u : u, -(u * zk));  // u (L u)_i, one rounding
-                        e_acc[c] += a.k.half_eps * ulu + a.k.quarter_inv_eps * u2m1 * u2m1 +
-                                    a.k.half_eta * lam * dy * dy;
-                    }
-                }
-            }
-        }
-    }
-    if (a.partials) block_stats<K, CPL>(e_acc, r_acc, G, a.partials, nb, b);
-}
-
-// One sweep (or the energy-only pass) for K columns.
-template <int K, typename TW, typename TU, typename OffT>
-__global__ __launch_bounds__(kBlock) void sweep_kernel(SweepArgs<TW, TU, OffT> a) {
-    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    sweep_block<K>(a, b, (int64_t)gridDim.x);
-}
-
-// Y = X - What X (L_s X) or Y = D X - W X (L X), Section 2.2
-template <typename TW, typename TU, typename OffT> struct LapArgs {
-    const OffT* rp;
-    const int32_t* col;
-    const TW* w;
-    const TU* x;
-    TU* y;
-    const int32_t* order;
-    const typename acc_of<TU>::type* dd;  // d_i of L, or nullptr for L_s
-    RowGeom g;
-};
-
-template <int K, typename TW, typename TU, typename OffT>
-__global__ __launch_bounds__(kBlock) void laplacian_kernel(LapArgs<TW, TU, OffT> a) {
-    typedef typename acc_of<TU>::type A;
-    constexpr int CPL = (K + 3) / 4;
-    const int G = a.g.G;
-    const int q = threadIdx.x & (G - 1);
-    const int grp = threadIdx.x >> a.g.log2G;
-    const int rows_per_tile = kBlock >> a.g.log2G;
-    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t row0 = b * a.g.rows_per_block;
-    for (int t = 0; t < a.g.tiles; ++t) {
-        const int64_t row = row0 + (int64_t)t * rows_per_tile + grp;
-        A z[K];
-        row_gather<K>(a.rp, a.col, a.w, a.x, row, a.g.n, q, G, z);
-        if (row < a.g.n) {
-            const int64_t node = a.order ? (int64_t)a.order[row] : row;
-#pragma unroll
-            for (int c = 0; c < CPL; ++c) {
-                const int k = q + c * G;
-                if (k < K) {
-                    const int64_t at = node * K + k;
-                    const A xv = cvt<A>(a.x[at]);
-                    a.y[at] = store_as<TU>::from((a.dd ? a.dd[node] * xv : xv) - pick<K>(z, k));
-                }
-            }
-        }
-    }
-}
-
-// Power-method pass on float vectors with lx = L_s x = x - What x (or L x =
-// d x - W x).  mode 0: y = s lx with s = *scale, partial[0] = sum y^2.
-// mode 1: partial[0] = sum x lx, partial[1] = sum x^2.
-template <typename TW, typename OffT> struct PowerArgs {
-    const OffT* rp;
-    const int32_t* col;
-    const TW* w;
-    const float* x;
-    float* y;
-    const float* scale;
-    float* partials;  // [2][grid]
-    const int32_t* order;
-    const float* dd;  // d_i of L, or nullptr for L_s
-    RowGeom g;
-    int32_t mode;
-};
-
-template <typename TW, typename OffT>
-__global__ __launch_bounds__(kBlock) void power_kernel(PowerArgs<TW, OffT> a) {
-    const int G = a.g.G;
-    const int q = threadIdx.x & (G - 1);
-    const int grp = threadIdx.x >> a.g.log2G;
-    const int rows_per_tile = kBlock >> a.g.log2G;
-    const int64_t b = a.g.remap ? xcd_remap(blockIdx.x, gridDim.x) : (int64_t)blockIdx.x;
-    const int64_t row0 = b * a.g.rows_per_block;
-    const float s = a.mode == 0 ? *a.scale : 1.0f;
-    float p0 = 0.f, p1 = 0.f;
-    for (int t = 0; t < a.g.tiles; ++t) {
-        const int64_t row = row0 + (int64_t)t * rows_per_tile + grp;
-        float z[1];
-        row_gather<1>(a.rp, a.col, a.w, a.x, row, a.g.n, q, G, z);
-        if (row < a.g.n && q == 0) {
-            const int64_t node = a.order ? (int64_t)a.order[row] : row;
-            const float xv = a.x[node];
-            const float lx = (a.dd ? a.dd[node] * xv : xv) - z[0];
-            if (a.mode == 0) {
-                const float yv = s * lx;
-                a.y[node] = yv;
-                p0 += yv * yv;
-            } else {
-                p0 += xv * lx;
-                p1 += xv * xv;
-            }
-        }
-    }
-    float e[1] = {p0}, r[1] = {p1};
-    block_stats<1, 1>(e, r, G, a.partials, (int64_t)gridDim.x, b);
-}
 
 // Fixed-order double reduction of one statistic per block: block s sums
 // partials[s * nb .. s * nb + nb).
@@ -278,6 +130,43 @@ __global__ void permute_rows_kernel(int64_t n, int32_t words, const int32_t* __r
         dst[o] = src[i];
     else
         dst[i] = src[o];
+}
+
+// Bandwidth ceilings (measurement helpers).  Each thread moves four 16-byte
+// vectors per step (non-temporal, grid-stride); the read-only kernel folds
+// what it reads into a value it stores only if it matches `never`, so the
+// loads cannot be dropped and nothing is written in practice.
+static __global__ __launch_bounds__(256) void stream_read_kernel(const u32x4* __restrict__ src, int64_t n16,
+                                                                 uint32_t never, u32x4* __restrict__ sink) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    u32x4 acc = {0u, 0u, 0u, 0u};
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(src + i);
+        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        acc ^= (a ^ b) ^ (c ^ d);
+    }
+    for (; i < n16; i += stride) acc ^= __builtin_nontemporal_load(src + i);
+    if ((acc.x ^ acc.y ^ acc.z ^ acc.w) == never) sink[0] = acc;
+}
+
+static __global__ __launch_bounds__(256) void stream_copy_kernel(const u32x4* __restrict__ src,
+                                                                 u32x4* __restrict__ dst, int64_t n16) {
+    const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+    int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    for (; i + 3 * stride < n16; i += 4 * stride) {
+        const u32x4 a = __builtin_nontemporal_load(src + i);
+        const u32x4 b = __builtin_nontemporal_load(src + i + stride);
+        const u32x4 c = __builtin_nontemporal_load(src + i + 2 * stride);
+        const u32x4 d = __builtin_nontemporal_load(src + i + 3 * stride);
+        __builtin_nontemporal_store(a, dst + i);
+        __builtin_nontemporal_store(b, dst + i + stride);
+        __builtin_nontemporal_store(c, dst + i + 2 * stride);
+        __builtin_nontemporal_store(d, dst + i + 3 * stride);
+    }
+    for (; i < n16; i += stride) __builtin_nontemporal_store(__builtin_nontemporal_load(src + i), dst + i);
 }
 
 template <typename TU>

@@ -3,8 +3,11 @@
 // instantiations compile in parallel.
 #pragma once
 
+#include <type_traits>
+
 #include "gl_internal.hpp"
 #include "gl_kernels.hpp"
+#include "gl_direct.hpp"
 #include "gl_tile.hpp"
 #include "gl_window.hpp"
 #include "gl_grid.hpp"
@@ -41,6 +44,9 @@ static SweepArgs<TW, TU, OffT> make_sweep_args(const SweepLaunch& L) {
     a.k.ga = (A)L.coef[11];
     a.k.gd = (A)L.coef[12];
     a.k.gl = (A)L.coef[13];
+    a.heavy = L.r.heavy;
+    a.nheavy = L.r.layout == LAYOUT_DIRECT ? L.r.nheavy : 0;
+    a.hblocks = (int32_t)(sweep_grid(L.r) - L.r.grid);
     return a;
 }
 
@@ -206,10 +212,14 @@ static hipError_t grid_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
     a.k = make_sweep_args<TW, TU, int32_t>(L).k;
     const dim3 grid((unsigned)L.r.grid), block(kGridThreads);
     const size_t lds = grid_lds_bytes<TU, A>(K);
+    const bool en = L.energy != 0 || L.vout == nullptr;
     switch (K) {
-#define GL_CASE(KK)                                                                       \
-    case KK:                                                                              \
-        hipLaunchKernelGGL((grid_sweep_kernel<KK, TW, TU>), grid, block, lds, s, a);     \
+#define GL_CASE(KK)                                                                               \
+    case KK:                                                                                      \
+        if (en)                                                                                   \
+            hipLaunchKernelGGL((grid_energy_sweep_kernel<KK, TW, TU>), grid, block, lds, s, a);  \
+        else                                                                                      \
+            hipLaunchKernelGGL((grid_sweep_kernel<KK, TW, TU>), grid, block, lds, s, a);         \
         break;
         GL_K_CASES(GL_CASE)
 #undef GL_CASE
@@ -217,6 +227,31 @@ static hipError_t grid_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
             return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+// Grid-layout sweeps of every weight type for field type TU (compiled in the
+// gl_unit_grid_* units, so they build in parallel with the other kernels).
+template <typename TU>
+static hipError_t grid_sweep_typed(int K, const SweepLaunch& L, hipStream_t s) {
+    if constexpr (std::is_same<TU, double>::value) {
+        if (L.r.wdt != GL_F64) return hipErrorInvalidValue;
+        return grid_sweep_k<double, double>(K, L, s);
+    } else {
+        switch (L.r.wdt) {
+            case GL_F32: return grid_sweep_k<float, TU>(K, L, s);
+            case GL_BF16: return grid_sweep_k<bf16, TU>(K, L, s);
+            case GL_F16: return grid_sweep_k<f16, TU>(K, L, s);
+            default: return hipErrorInvalidValue;
+        }
+    }
+}
+
+template <typename TU>
+static hipError_t grid_sweep_extern(int K, const SweepLaunch& L, hipStream_t s) {
+    if constexpr (std::is_same<TU, double>::value) return launch_grid_sweep_f64(K, L, s);
+    else if constexpr (std::is_same<TU, float>::value) return launch_grid_sweep_f32(K, L, s);
+    else if constexpr (std::is_same<TU, bf16>::value) return launch_grid_sweep_bf16(K, L, s);
+    else return launch_grid_sweep_f16(K, L, s);
 }
 
 template <typename TW, typename TU>
@@ -244,11 +279,11 @@ static hipError_t grid_laplacian_k(int K, const RowLaunch& r, const void* x, voi
 
 template <typename TW, typename TU, typename OffT>
 static hipError_t sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
-    if (L.r.layout == LAYOUT_GRID) return grid_sweep_k<TW, TU>(K, L, s);
+    if (L.r.layout == LAYOUT_GRID) return grid_sweep_extern<TU>(K, L, s);
     if (L.r.layout == LAYOUT_TILE) return tile_sweep_k<TW, TU>(K, L, s);
     if (L.r.layout == LAYOUT_WINDOW) return window_sweep_k<TW, TU>(K, L, s);
     const SweepArgs<TW, TU, OffT> a = make_sweep_args<TW, TU, OffT>(L);
-    const dim3 grid((unsigned)L.r.grid), block(kBlock);
+    const dim3 grid((unsigned)sweep_grid(L.r)), block(kBlock);
     switch (K) {
 #define GL_CASE(KK)                                                           \
     case KK:                                                                  \

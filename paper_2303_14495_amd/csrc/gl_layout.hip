@@ -150,69 +150,4 @@ bool build_layout(int64_t n, const int64_t* rp, const int32_t* col, const int32_
     return true;
 }
 
-bool build_grid_layout(int64_t n, int32_t height, int32_t width, const int64_t* rp, const int32_t* col,
-                       GridLayout& out, std::string& err) {
-    if ((int64_t)height * width != n) {
-        err = "grid_height * grid_width must equal n";
-        return false;
-    }
-    const int32_t tiles_x = (width + 63) / 64;
-    out.tiles_x = tiles_x;
-    out.cnt.assign((size_t)n, 0);
-    for (int64_t i = 0; i < n; ++i) {
-        const int64_t deg = rp[i + 1] - rp[i];
-        const int64_t yi = i / width, xi = i - yi * width;
-        for (int64_t e = rp[i]; e < rp[i + 1]; ++e) {
-            const int64_t j = col[e], yj = j / width, xj = j - yj * width;
-            if (yj - yi < -7 || yj - yi > 7 || xj - xi < -7 || xj - xi > 7) {
-                err = "grid layout: edge (" + std::to_string(i) + ", " + std::to_string(j) +
-                      ") joins pixels more than 7 rows or columns apart";
-                return false;
-            }
-        }
-        out.cnt[i] = (uint8_t)((deg + 7) / 8);  // deg <= 224 (distinct window cells)
-    }
-    out.wbase.assign((size_t)height * tiles_x, 0);
-    int64_t total = 0;
-    int mincnt = 255;
-    for (int64_t i = 0; i < n; ++i) {
-        total += out.cnt[i];
-        mincnt = std::min(mincnt, (int)out.cnt[i]);
-    }
-    out.chunks = total;
-    out.dense = std::min(mincnt, kGridDenseMax);
-    out.offs.assign((size_t)total * 8, (uint8_t)0x77);
-    out.src.assign((size_t)total * 8, -1);
-    auto emit = [&](int64_t id, int64_t i, int c) {  // chunk c of pixel i as chunk id
-        const int64_t y = i / width, x = i - y * width;
-        for (int e = 0; e < 8; ++e) {
-            const int64_t k = rp[i] + (int64_t)c * 8 + e;
-            if (k >= rp[i + 1]) break;
-            const int64_t j = col[k], yj = j / width, xj = j - yj * width;
-            out.offs[(size_t)id * 8 + e] = (uint8_t)(((yj - y + 7) << 4) | (xj - x + 7));
-            out.src[(size_t)id * 8 + e] = (int32_t)k;
-        }
-    };
-    // the first `dense` chunks of every pixel, by pixel
-    for (int c = 0; c < out.dense; ++c)
-        for (int64_t i = 0; i < n; ++i) emit((int64_t)c * n + i, i, c);
-    // the rest by row segment: round c of every lane that has it, in lane order
-    int64_t next = (int64_t)out.dense * n;
-    for (int32_t y = 0; y < height; ++y) {
-        for (int32_t tx = 0; tx < tiles_x; ++tx) {
-            out.wbase[(size_t)y * tiles_x + tx] = next;
-            const int32_t x0 = tx * 64, x1 = std::min(width, x0 + 64);
-            int maxc = 0;
-            for (int32_t x = x0; x < x1; ++x) maxc = std::max(maxc, (int)out.cnt[(int64_t)y * width + x]);
-            for (int c = out.dense; c < maxc; ++c) {
-                for (int32_t x = x0; x < x1; ++x) {
-                    const int64_t i = (int64_t)y * width + x;
-                    if (out.cnt[i] > c) emit(next++, i, c);
-                }
-            }
-        }
-    }
-    return true;
-}
-
 }  // namespace gl

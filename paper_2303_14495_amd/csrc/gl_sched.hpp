@@ -7,6 +7,7 @@
 #include <cstddef>
 #include <cstdint>
 #include <map>
+#include <vector>
 
 namespace gl {
 
@@ -102,6 +103,30 @@ inline DirectGeom direct_geometry(int64_t n, int64_t nnz) {
     return g;
 }
 
+// Rows longer than heavy_threshold(G) entries ("heavy" rows: the hubs of kNN
+// graphs in high dimension) are left out of the row passes of the sweep and
+// summed by a workgroup of their own (each of its 256 lanes takes every 256th
+// entry), so no lane walks a long row alone.  Their workgroups come first in
+// the launch, padded to a multiple of 8 (one per XCD), so the row passes that
+// follow keep their XCD-aligned numbering.
+inline int64_t heavy_threshold(int G) { return 16 * (int64_t)G; }
+
+inline int64_t heavy_blocks(int64_t nheavy) { return (nheavy + 7) / 8 * 8; }
+
+// Upper bound of the heavy rows of a graph (each holds more than
+// heavy_threshold(G) of the nnz entries).
+inline int64_t heavy_bound(int64_t nnz, int G) { return nnz / (heavy_threshold(G) + 1) + 1; }
+
+// The heavy rows of a CSR graph, in increasing row order.
+template <typename OffT>
+inline std::vector<int32_t> heavy_rows(int64_t n, const OffT* rp, int G) {
+    std::vector<int32_t> out;
+    const int64_t h = heavy_threshold(G);
+    for (int64_t i = 0; i < n; ++i)
+        if ((int64_t)(rp[i + 1] - rp[i]) > h) out.push_back((int32_t)i);
+    return out;
+}
+
 // Device bytes of one served solve, split into the part released once its
 // operator is built (the raw CSR copy) and the part held until it finishes.
 struct Footprint {
@@ -122,7 +147,8 @@ inline Footprint served_footprint(int64_t n, int64_t nnz, int32_t K, int32_t T, 
              align256((size_t)n * 8) +                       // degrees
              align256((size_t)n * 4) * 2 +                    // labels in, classes out
              3 * align256((size_t)n * K * su) +               // field buffers
-             align256((size_t)2 * K * g.blocks * 4) +         // block partials
+             align256((size_t)heavy_bound(nnz, g.G) * 4) +    // heavy rows
+             align256((size_t)2 * K * (g.blocks + heavy_blocks(heavy_bound(nnz, g.G))) * 4) +  // block partials
              align256(stats) + 256;                           // stats + flags
     return f;
 }

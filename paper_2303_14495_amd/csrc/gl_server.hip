@@ -27,6 +27,7 @@
 
 #include "gl_internal.hpp"
 #include "gl_kernels.hpp"
+#include "gl_direct.hpp"
 #include "gl_sched.hpp"
 
 namespace gl {
@@ -48,12 +49,14 @@ struct ServedDesc {
     double* energy_dst;  // K doubles or nullptr
     double* res_dst;     // K doubles or nullptr
     double* flag;
+    const int32_t* heavy;  // rows longer than 16 G, each summed by a workgroup of its own
     int64_t n;
     int64_t rows_per_block;
-    int64_t blocks;
+    int64_t blocks;       // workgroups of this solve: hblocks heavy-row ones, then the row blocks
     int64_t block_begin;  // prefix over the descriptors of `blocks`
     int32_t stat_begin;   // prefix over the descriptors of 2K
     int32_t G, log2G, tiles, K, energy;
+    int32_t nheavy, hblocks;
     float coef[11];
 };
 
@@ -84,12 +87,18 @@ __device__ __forceinline__ SweepArgs<TW, TU, int32_t> served_args(const ServedDe
     a.k.alpha = d.coef[9];
     a.k.kappa = d.coef[10];
     a.k.ga = a.k.gd = a.k.gl = 0.f;
+    a.heavy = d.heavy;
+    a.nheavy = d.nheavy;
+    a.hblocks = d.hblocks;
     return a;
 }
 
-// One tick: workgroup x runs logical block (x - block_begin) of the solve whose
-// block range contains x.
-template <typename TW, typename TU>
+// One tick, for the solves of one K: workgroup x runs workgroup
+// (x - block_begin) of the solve whose block range contains x: a heavy row or
+// a row block, exactly as sweep_kernel numbers them for that solve alone (so
+// the partial sums land in the same slots and the results are bitwise those of
+// gl_solve).  One instantiation per K keeps each K's register budget its own.
+template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(kBlock) void served_sweep_kernel(const ServedDesc* __restrict__ descs, int32_t count) {
     __shared__ int32_t s_idx;
     if (threadIdx.x == 0) {
@@ -102,20 +111,13 @@ __global__ __launch_bounds__(kBlock) void served_sweep_kernel(const ServedDesc* 
         s_idx = lo;
     }
     __syncthreads();
-    const ServedDesc d = descs[s_idx];
+    const ServedDesc& d = descs[s_idx];
     const int64_t b = (int64_t)blockIdx.x - d.block_begin;
     const SweepArgs<TW, TU, int32_t> a = served_args<TW, TU>(d);
-    switch (d.K) {
-#define GL_SERVED_CASE(KK) \
-    case KK:               \
-        sweep_block<KK>(a, b, d.blocks); \
-        break;
-        GL_SERVED_CASE(1) GL_SERVED_CASE(2) GL_SERVED_CASE(3) GL_SERVED_CASE(4) GL_SERVED_CASE(5)
-        GL_SERVED_CASE(6) GL_SERVED_CASE(7) GL_SERVED_CASE(8) GL_SERVED_CASE(9) GL_SERVED_CASE(10)
-#undef GL_SERVED_CASE
-        default:
-            break;
-    }
+    if (b < d.hblocks)
+        heavy_block<K>(a, b, b, d.blocks);
+    else
+        sweep_block<K>(a, b - d.hblocks, b, d.blocks);
 }
 
 // Statistics of one tick: workgroup x reduces statistic (x - stat_begin) of its solve.
@@ -206,6 +208,8 @@ struct Solve {
     int32_t* d_classes = nullptr;
     void* d_buf[3] = {nullptr, nullptr, nullptr};
     float* d_partials = nullptr;
+    int32_t* d_heavy = nullptr;
+    int32_t nheavy = 0, hblocks = 0;
     double* d_stats = nullptr;
     int32_t* d_flags = nullptr;
     gl::DirectGeom geom{};
@@ -221,6 +225,13 @@ struct Solve {
     std::vector<float> U_out;
     std::vector<int32_t> classes_out;
     std::vector<double> stats_out;
+};
+
+// The solves of one K within a tick: descriptors [first, first + count), their
+// workgroups numbered from 0 within the group.
+struct TickGroup {
+    int32_t K, first, count;
+    int64_t blocks;
 };
 
 double precond_g(int kind, double lam, const gl_params& p) {
@@ -373,7 +384,17 @@ struct gl_server {
         s.d_labels = (int32_t*)take(held, (size_t)s.n * 4);
         s.d_classes = (int32_t*)take(held, (size_t)s.n * 4);
         for (int i = 0; i < 3; ++i) s.d_buf[i] = take(held, (size_t)s.n * s.K * su);
-        s.d_partials = (float*)take(held, (size_t)2 * s.K * s.geom.blocks * 4);
+        // heavy rows from the request's own row offsets (host), before the copies
+        const std::vector<int32_t> hv = gl::heavy_rows(s.n, s.h_rp, s.geom.G);
+        if ((int64_t)hv.size() > gl::heavy_bound(s.nnz, s.geom.G)) {
+            // only a malformed row_ptr (not non-decreasing) gets here; the
+            // validation kernel would reject it too
+            return GL_E_BAD_GRAPH;
+        }
+        s.nheavy = (int32_t)hv.size();
+        s.hblocks = (int32_t)gl::heavy_blocks(s.nheavy);
+        s.d_heavy = (int32_t*)take(held, (size_t)gl::heavy_bound(s.nnz, s.geom.G) * 4);
+        s.d_partials = (float*)take(held, (size_t)2 * s.K * (s.geom.blocks + gl::heavy_blocks(gl::heavy_bound(s.nnz, s.geom.G))) * 4);
         s.d_stats = (double*)take(held, (size_t)s.stats_len * 8);
         s.d_flags = (int32_t*)take(held, 256);
 
@@ -388,6 +409,8 @@ struct gl_server {
         if (e == hipSuccess) e = hipMemcpyAsync(s.d_labels, s.h_labels, s.n * 4, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(s.d_u0, s.h_u0, s.n * s.K * 4, hipMemcpyHostToDevice, st);
         if (e == hipSuccess) e = hipMemcpyAsync(s.d_flags, &fl, sizeof(fl), hipMemcpyHostToDevice, st);
+        if (e == hipSuccess && !hv.empty())
+            e = hipMemcpyAsync(s.d_heavy, hv.data(), hv.size() * 4, hipMemcpyHostToDevice, st);
         if (e != hipSuccess) {
             set_fatal(std::string("server copy: ") + hipGetErrorString(e));
             return GL_E_HIP;
@@ -516,19 +539,31 @@ struct gl_server {
             gl::ServedDesc* hd = h_desc + (size_t)slot * cfg.max_slots;
             gl::ServedDesc* dd = d_desc + (size_t)slot * cfg.max_slots;
             int count = 0;
-            int64_t blocks = 0;
+            int64_t blocks = 0;  // within the current K group
             int32_t stats = 0;
-            for (auto& s : active) {
-                if (s->cur.done) continue;
+            // solves grouped by K (one sweep launch per K), in admission order within a group
+            std::vector<Solve*> order;
+            for (auto& s : active)
+                if (!s->cur.done) order.push_back(s.get());
+            std::stable_sort(order.begin(), order.end(), [](const Solve* a, const Solve* b) { return a->K < b->K; });
+            std::vector<TickGroup> groups;
+            for (Solve* s : order) {
+                if (groups.empty() || groups.back().K != s->K) {
+                    groups.push_back(TickGroup{s->K, count, 0, 0});
+                    blocks = 0;
+                }
                 gl::ServedDesc& d = hd[count++];
                 d.rp = s->d_rp;
                 d.col = s->d_col;
                 d.w = s->d_w;
                 d.labels = s->d_labels;
                 d.partials = s->d_partials;
+                d.heavy = s->d_heavy;
+                d.nheavy = s->nheavy;
+                d.hblocks = s->hblocks;
                 d.n = s->n;
                 d.rows_per_block = s->geom.rows_per_block;
-                d.blocks = s->geom.blocks;
+                d.blocks = s->geom.blocks + s->hblocks;
                 d.block_begin = blocks;
                 d.stat_begin = stats;
                 d.G = s->geom.G;
@@ -554,10 +589,12 @@ struct gl_server {
                 }
                 blocks += d.blocks;
                 stats += 2 * s->K;
+                groups.back().count += 1;
+                groups.back().blocks = blocks;
             }
             if (count > 0) {
                 hipError_t e = hipMemcpyAsync(dd, hd, sizeof(gl::ServedDesc) * count, hipMemcpyHostToDevice, s_comp);
-                if (e == hipSuccess) e = launch_tick(dd, count, blocks, stats);
+                if (e == hipSuccess) e = launch_tick(dd, count, groups, stats);
                 if (e == hipSuccess) e = hipEventRecord(tick_ev[slot], s_comp);
                 if (e != hipSuccess) set_fatal(std::string("tick launch: ") + hipGetErrorString(e));
                 tick_used[slot] = true;
@@ -611,29 +648,48 @@ struct gl_server {
         }
     }
 
-    hipError_t launch_tick(const gl::ServedDesc* dd, int count, int64_t blocks, int32_t stats) {
-        const dim3 grid((unsigned)blocks), block(gl::kBlock);
-        switch (cfg.store_w * 4 + cfg.store_u) {
-#define GL_TICK(WD, UD, TW, TU)                                                                          \
-    case WD * 4 + UD:                                                                                    \
-        hipLaunchKernelGGL((gl::served_sweep_kernel<TW, TU>), grid, block, 0, s_comp, dd, (int32_t)count); \
+    template <typename TW, typename TU>
+    hipError_t launch_group(const gl::ServedDesc* dd, const TickGroup& g) {
+        const dim3 grid((unsigned)g.blocks), block(gl::kBlock);
+        const gl::ServedDesc* d = dd + g.first;
+        switch (g.K) {
+#define GL_SK(KK)                                                                                        \
+    case KK:                                                                                             \
+        hipLaunchKernelGGL((gl::served_sweep_kernel<KK, TW, TU>), grid, block, 0, s_comp, d, g.count);   \
         break;
-            GL_TICK(GL_F32, GL_F32, float, float)
-            GL_TICK(GL_F32, GL_BF16, float, gl::bf16)
-            GL_TICK(GL_F32, GL_F16, float, gl::f16)
-            GL_TICK(GL_BF16, GL_F32, gl::bf16, float)
-            GL_TICK(GL_BF16, GL_BF16, gl::bf16, gl::bf16)
-            GL_TICK(GL_BF16, GL_F16, gl::bf16, gl::f16)
-            GL_TICK(GL_F16, GL_F32, gl::f16, float)
-            GL_TICK(GL_F16, GL_BF16, gl::f16, gl::bf16)
-            GL_TICK(GL_F16, GL_F16, gl::f16, gl::f16)
-#undef GL_TICK
+            GL_SK(1) GL_SK(2) GL_SK(3) GL_SK(4) GL_SK(5) GL_SK(6) GL_SK(7) GL_SK(8) GL_SK(9) GL_SK(10)
+#undef GL_SK
             default:
                 return hipErrorInvalidValue;
         }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
-        hipLaunchKernelGGL(gl::served_stats_kernel, dim3((unsigned)stats), block, 0, s_comp, dd, (int32_t)count);
+        return hipGetLastError();
+    }
+
+    hipError_t launch_tick(const gl::ServedDesc* dd, int count, const std::vector<TickGroup>& groups, int32_t stats) {
+        for (const TickGroup& g : groups) {
+            hipError_t e = hipErrorInvalidValue;
+            switch (cfg.store_w * 4 + cfg.store_u) {
+#define GL_TICK(WD, UD, TW, TU) \
+    case WD * 4 + UD:           \
+        e = launch_group<TW, TU>(dd, g); \
+        break;
+                GL_TICK(GL_F32, GL_F32, float, float)
+                GL_TICK(GL_F32, GL_BF16, float, gl::bf16)
+                GL_TICK(GL_F32, GL_F16, float, gl::f16)
+                GL_TICK(GL_BF16, GL_F32, gl::bf16, float)
+                GL_TICK(GL_BF16, GL_BF16, gl::bf16, gl::bf16)
+                GL_TICK(GL_BF16, GL_F16, gl::bf16, gl::f16)
+                GL_TICK(GL_F16, GL_F32, gl::f16, float)
+                GL_TICK(GL_F16, GL_BF16, gl::f16, gl::bf16)
+                GL_TICK(GL_F16, GL_F16, gl::f16, gl::f16)
+#undef GL_TICK
+                default:
+                    break;
+            }
+            if (e != hipSuccess) return e;
+        }
+        hipLaunchKernelGGL(gl::served_stats_kernel, dim3((unsigned)stats), dim3(gl::kBlock), 0, s_comp, dd,
+                           (int32_t)count);
         return hipGetLastError();
     }
 

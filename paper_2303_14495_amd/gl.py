@@ -106,6 +106,7 @@ SIGNATURES = {
     "gl_assign_labels": (ctypes.c_int, [_I64, _I32, _I32, _P, _P, _P]),
     "gl_params_validate": (ctypes.c_int, [_P]),
     "gl_time_sweeps": (ctypes.c_int, [_P, _P, _I32, _P, _I32, _P, _P, _SZ, _I32, _P, _P]),
+    "gl_time_stream": (ctypes.c_int, [_I32, _P, _SZ, _I32, _P, _P]),
     "gl_server_create": (ctypes.c_int, [_P, _P]),
     "gl_server_submit": (ctypes.c_int, [_P, _P, _P]),
     "gl_server_poll": (ctypes.c_int, [_P, ctypes.c_uint64, _I32, _P]),
@@ -377,6 +378,18 @@ def time_sweeps(op: Operator, labels: torch.Tensor, U: torch.Tensor, *, eps, c, 
     _check(lib.gl_time_sweeps(op.handle, ctypes.byref(p), K, _ptr(labels), DTYPES[store_u],
                               _ptr(U), _ptr(ws), ws.numel(), reps, ctypes.byref(out),
                               _stream_handle(stream)))
+    return out.value
+
+
+def time_stream(buf: torch.Tensor, kind: str = "read", reps: int = 20, stream=None) -> float:
+    """Mean time per launch (ms) of the library's plain streaming kernel
+    ("read": reads all of buf) or copy kernel ("copy": first half to second
+    half) over a device byte tensor, `reps` launches between one event pair."""
+    if not buf.is_cuda or buf.dtype != torch.uint8 or not buf.is_contiguous():
+        raise ValueError("buf must be a contiguous CUDA uint8 tensor")
+    out = ctypes.c_double()
+    _check(load_library().gl_time_stream({"read": 0, "copy": 1}[kind], _ptr(buf), buf.numel(),
+                                         reps, ctypes.byref(out), _stream_handle(stream)))
     return out.value
 
 

@@ -21,7 +21,7 @@ import torch
 
 from .graphs import (Graph, gaussian_mixture, knn_bruteforce, window_knn,
                      self_tuning_graph, rectangles_image, textured_regions_image,
-                     patch_features, random_labels, initial_u, zorder)
+                     patch_features, random_labels, scribble_labels, initial_u, zorder)
 
 CONFIG_NAMES = {
     1: "cluster2-n4096-k10",
@@ -130,14 +130,23 @@ def make_problem(cfg: int, device="cpu", small: bool = False) -> Problem:
                        precond="damped_jacobi", outer=20, sweeps=4,
                        store_w="bf16", store_u="bf16")
     if cfg == 4:
-        side = 128 if small else 2048
-        r_data, r_lab, _ = _streams(seed)
-        img, truth = textured_regions_image(side, side, 4, r_data, noise=0.05)
-        name = CONFIG_NAMES[4] if not small else "image128-texture4-k20"
-        return _image_problem(name, img, truth, 20, 0.005, 4, seed, r_lab, device,
-                              eps=100.0, c=11.0, eta=100.0, precond="richardson",
-                              outer=10, sweeps=8, store_w="bf16", store_u="f16")
+        return texture_problem(128 if small else 2048, device)
     raise ValueError(f"unknown workload {cfg}")
+
+
+def texture_problem(side: int, device="cpu") -> Problem:
+    """Workload 4's recipe on a side x side image (2048 for the workload
+    itself): 4 textured Voronoi regions, noise 0.05, 3 x 3 RGB patches, 20-NN
+    in the 15 x 15 window, K = 4, 0.5 % labels, 10 x 8 Richardson sweeps,
+    bf16 weights and f16 field.  Other sides serve as larger or smaller
+    instances of the same workload."""
+    seed = 3
+    r_data, r_lab, _ = _streams(seed)
+    img, truth = textured_regions_image(side, side, 4, r_data, noise=0.05)
+    name = CONFIG_NAMES[4] if side == 2048 else f"image{side}-texture4-k20"
+    return _image_problem(name, img, truth, 20, 0.005, 4, seed, r_lab, device,
+                          eps=100.0, c=11.0, eta=100.0, precond="richardson",
+                          outer=10, sweeps=8, store_w="bf16", store_u="f16")
 
 
 # --------------------------------------------------------------------------
@@ -228,20 +237,25 @@ class WindowProblem:
 
 def window_problem(h: int = 1024, w: int = 1024, rw: int = 12, rp: int = 2, seed: int = 5,
                    frac: float = 0.01, nrect: int = 6, noise: float = 3.0,
-                   **kw) -> WindowProblem:
+                   scribbles: bool = False, **kw) -> WindowProblem:
     """Binary segmentation on the paper's window graph: `nrect` rectangles of
     one colour over a background (colours uniform on the 8-bit scale [0, 255]^3,
     at least 0.3 * 255 apart), Gaussian noise of `noise` levels, a fraction
     `frac` of pixels labelled with the ground truth, sigma = log(h w) + 1 (the
     order the paper gives for images).  Defaults: a 1024 x 1024 image with the
     25 x 25 window and 5 x 5 patches and eps = 100, c = 11, eta = 100 and four
-    sweeps per DCA step (the paper's preconditioner comparison)."""
+    sweeps per DCA step (the paper's preconditioner comparison).  scribbles:
+    labels from synth.graphs.scribble_labels instead of a random fraction."""
     r_data, r_lab, _ = _streams(seed)
     lo, hi = max(6, min(h, w) // 16), max(8, min(h, w) // 3)
     img, truth = rectangles_image(h, w, nrect, r_data, side=(lo, hi), noise=noise / 255.0)
     img *= 255.0
     t = truth.reshape(-1).astype(np.int32)
-    labels = random_labels(t, frac, 2, r_lab)
-    return WindowProblem(name=f"window{h}x{w}-r{rw}-p{rp}", image=img, rw=rw, rp=rp,
+    if scribbles:
+        labels = scribble_labels(truth, r_lab)
+    else:
+        labels = random_labels(t, frac, 2, r_lab)
+    return WindowProblem(name=f"window{h}x{w}-r{rw}-p{rp}" + ("-scribbles" if scribbles else ""),
+                         image=img, rw=rw, rp=rp,
                          sigma=math.log(h * w) + 1.0, K=1, labels=labels,
                          u0=initial_u(labels, 1), truth=t, seed=seed, **kw)

@@ -272,6 +272,41 @@ def random_labels(truth: np.ndarray, frac: float, nclass: int,
     return lab
 
 
+def scribble_labels(truth: np.ndarray, rng: np.random.Generator, width: int = 3,
+                    frac_len: float = 0.25, background_strokes: int = 4) -> np.ndarray:
+    """Scribble-style labels on an image's ground truth [h, w] (the paper's
+    segmentation inputs mark each object with a few strokes): through the
+    centre row of every connected region of class 1, a horizontal stroke
+    `width` pixels tall over `frac_len` of the region's bounding-box width; and
+    `background_strokes` strokes of the same shape on class-0 pixels at seeded
+    random places.  Returns int32 [h * w], -1 unlabelled."""
+    from scipy import ndimage
+    h, w = truth.shape
+    lab = np.full((h, w), -1, dtype=np.int32)
+    comps, ncomp = ndimage.label(truth == 1)
+    for c in range(1, ncomp + 1):
+        ys, xs = np.nonzero(comps == c)
+        yc = int(round(ys.mean()))
+        x0, x1 = xs.min(), xs.max()
+        half = max(1, int(frac_len * (x1 - x0 + 1)) // 2)
+        xc = (x0 + x1) // 2
+        for y in range(yc - width // 2, yc + width // 2 + 1):
+            for x in range(xc - half, xc + half + 1):
+                if 0 <= y < h and 0 <= x < w and comps[y, x] == c:
+                    lab[y, x] = 1
+    bg = truth == 0
+    length = max(8, int(frac_len * w / 4))
+    placed = 0
+    while placed < background_strokes:
+        y = int(rng.integers(width, h - width))
+        x = int(rng.integers(0, max(1, w - length)))
+        box = bg[y - width // 2:y + width // 2 + 1, x:x + length]
+        if box.size and box.all():
+            lab[y - width // 2:y + width // 2 + 1, x:x + length] = 0
+            placed += 1
+    return lab.reshape(-1)
+
+
 def initial_u(labels: np.ndarray, K: int, mode: str = "labels",
               rng: np.random.Generator | None = None) -> np.ndarray:
     """Initial label field u^0 [n, K] float64.

@@ -231,3 +231,15 @@ def test_server_entry_points_reject_foreign_handles(magic):
     assert lib.gl_server_destroy(h) == 1
     assert b"server" in lib.gl_last_error()
     assert int.from_bytes(buf.raw[:8], "little") == magic
+
+
+@pytest.mark.parametrize("kind,nbytes,reps,addr", [
+    (2, 1 << 20, 1, 4096), (0, 1 << 19, 1, 4096), (0, (1 << 20) + 1, 1, 4096), (1, 1 << 20, 0, 4096),
+    (1, 1 << 20, 10001, 4096), (0, 1 << 20, 1, 4100), (0, 1 << 20, 1, 0),
+])
+def test_time_stream_rejects_bad_arguments(kind, nbytes, reps, addr):
+    # checked on the host before any launch (dummy device address)
+    lib = gl.load_library()
+    out = ctypes.c_double()
+    assert lib.gl_time_stream(kind, ctypes.c_void_p(addr) if addr else None, nbytes, reps,
+                              ctypes.byref(out), None) == 1

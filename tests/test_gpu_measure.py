@@ -37,3 +37,20 @@ def test_time_sweeps(layout, store):
         with pytest.raises(gl.GLError):
             gl.time_sweeps(op, lab, U, eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, lambda_max=1.4,
                            reps=bad)
+
+
+def test_time_stream_ceilings():
+    # the plain streaming and copy kernels behind the measured HBM ceiling:
+    # finite times, the copy really copies, the read leaves the buffer alone
+    nb = 256 << 20
+    buf = torch.randint(0, 256, (nb,), dtype=torch.uint8, device=DEV)
+    ref = buf.clone()
+    tr = gl.time_stream(buf, "read", 5)
+    assert torch.equal(buf, ref)
+    tc = gl.time_stream(buf, "copy", 5)
+    torch.cuda.synchronize()
+    assert torch.equal(buf[nb // 2:], ref[: nb // 2]) and torch.equal(buf[: nb // 2], ref[: nb // 2])
+    say(f"time_stream 256 MiB: read {nb / tr / 1e6:.0f} GB/s, copy {nb / tc / 1e6:.0f} GB/s")
+    assert 0 < tr < 50 and 0 < tc < 50
+    with pytest.raises(gl.GLError):
+        gl.time_stream(buf[:1000], "read", 1)
