@@ -635,6 +635,18 @@ def precond_bench(dev, targets=(0.99, 0.995), max_steps=500):
             "lambda_hat": lam, "runs": rows}
 
 
+def calib_copy(dev):
+    """Counter calibration: one elementwise kernel that reads 1 GiB and writes
+    1 GiB, far beyond the L2 and the Infinity Cache."""
+    import torch
+    src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
+    dst = torch.empty_like(src)
+    torch.cuda.synchronize()
+    torch.mul(src, 1.0, out=dst)
+    torch.cuda.synchronize()
+    log(f"calibration: mul over {src.numel() * 4} bytes in, {dst.numel() * 4} out")
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -651,12 +663,18 @@ def main():
     torch.cuda.set_device(dev)
     if args.window_only:
         print(json.dumps(window_bench(dev, args.steps, args.warmup, args.sweep_reps)), flush=True)
+        if args.calib_copy:
+            calib_copy(dev)
         return
     if args.precond_only:
         print(json.dumps(precond_bench(dev)), flush=True)
+        if args.calib_copy:
+            calib_copy(dev)
         return
     if args.hbm_scale_only:
         print(json.dumps(hbm_scale_bench(dev, args.sweep_reps)), flush=True)
+        if args.calib_copy:
+            calib_copy(dev)
         return
     if args.served_only:
         rates = [float(v) for v in args.served_rates.split(",") if v]
@@ -878,14 +896,7 @@ def main():
     }
     print(json.dumps(out), flush=True)
     if args.calib_copy:
-        # counter calibration: an elementwise kernel that reads 1 GiB and
-        # writes 1 GiB, far beyond the L2 and the Infinity Cache
-        src = torch.ones(1 << 28, dtype=torch.float32, device=dev)
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        torch.mul(src, 1.0, out=dst)
-        torch.cuda.synchronize()
-        log(f"calibration: mul over {src.numel() * 4} bytes in, {dst.numel() * 4} out")
+        calib_copy(dev)
 
 
 if __name__ == "__main__":

@@ -46,6 +46,8 @@ def load():
     lib.glo_power.restype = ctypes.c_int
     lib.glo_laplacian_apply.argtypes = [i64, P, P, P, i32, P, P, i32]
     lib.glo_laplacian_apply.restype = ctypes.c_int
+    lib.glo_window_graph.argtypes = [i32, i32, i32, P, i32, i32, f64, P, P, P, i64]
+    lib.glo_window_graph.restype = ctypes.c_int64
     lib.glo_num_threads.argtypes = []
     lib.glo_num_threads.restype = ctypes.c_int
     _lib = lib
@@ -86,6 +88,25 @@ def dca_solve(n, row_ptr, col, w, labels, u0, *, eps, c, eta, precond, outer, sw
     if rc != 0:
         raise MemoryError("C oracle allocation failed")
     return U, en, rs
+
+
+def window_graph(img, rw, rp, sigma):
+    """Same contract as window_oracle.window_graph (plain C, OpenMP over pixels)."""
+    lib = load()
+    im = np.ascontiguousarray(img, dtype=np.float64)
+    if im.ndim == 2:
+        im = im[:, :, None].copy()
+    h, w, C = im.shape
+    n = h * w
+    cap = n * ((2 * rw + 1) ** 2 - 1)
+    row_ptr = np.empty(n + 1, dtype=np.int64)
+    col = np.empty(cap, dtype=np.int32)
+    ww = np.empty(cap, dtype=np.float64)
+    nnz = lib.glo_window_graph(h, w, C, _ptr(im), rw, rp, float(sigma), _ptr(row_ptr), _ptr(col),
+                               _ptr(ww), cap)
+    if nnz < 0:
+        raise MemoryError("window graph larger than its bound")
+    return row_ptr, col[:nnz].copy(), ww[:nnz].copy()
 
 
 def power_max_eig(n, row_ptr, col, w, x0, iters=150, laplacian="normalized"):

@@ -229,6 +229,69 @@ int glo_power(int64_t n, const int64_t *rp, const int32_t *col, const double *w,
     return 0;
 }
 
+/* The paper's image graph (Section 2.2) in CSR, with the readings of
+ * window_oracle.py: pixel i (row-major, h x w, C channels, img[(y w + x) C + c])
+ * is joined to every other pixel j with max(|dy|, |dx|) <= rw, weight
+ *     w_ij = exp(-sum_n alpha_n |C(p_i + n) - C(p_j + n)|^2 / sigma^2)
+ * over the (2 rp + 1)^2 patch offsets n, alpha_n = g(a) g(b) / (sum g)^2 with
+ * g(t) = exp(-t^2 / (2 rp^2)) (1 for rp = 0), colours outside the image taken
+ * from the nearest border pixel.  Columns ascend within a row (window offsets
+ * in scan order); row_ptr has n + 1 entries; returns the number of stored
+ * entries, or -1 when `cap` is too small. */
+int64_t glo_window_graph(int32_t h, int32_t w, int32_t C, const double *img, int32_t rw, int32_t rp,
+                         double sigma, int64_t *row_ptr, int32_t *col, double *wout, int64_t cap)
+{
+    const int64_t n = (int64_t)h * w;
+    const int32_t P = 2 * rp + 1;
+    double g[64], gs = 0.0, alpha[64 * 64];
+    for (int32_t a = -rp; a <= rp; a++) {
+        g[a + rp] = rp > 0 ? exp(-(double)(a * a) / (2.0 * rp * rp)) : 1.0;
+        gs += g[a + rp];
+    }
+    for (int32_t a = 0; a < P; a++)
+        for (int32_t b = 0; b < P; b++) alpha[a * P + b] = g[a] * g[b] / (gs * gs);
+    /* row offsets: the count of in-image window cells of every pixel */
+    row_ptr[0] = 0;
+    for (int64_t i = 0; i < n; i++) {
+        const int32_t y = (int32_t)(i / w), x = (int32_t)(i % w);
+        const int32_t y0 = y - rw < 0 ? 0 : y - rw, y1 = y + rw >= h ? h - 1 : y + rw;
+        const int32_t x0 = x - rw < 0 ? 0 : x - rw, x1 = x + rw >= w ? w - 1 : x + rw;
+        row_ptr[i + 1] = row_ptr[i] + (int64_t)(y1 - y0 + 1) * (x1 - x0 + 1) - 1;
+    }
+    if (row_ptr[n] > cap) return -1;
+    const double inv_s2 = 1.0 / (sigma * sigma);
+#pragma omp parallel for schedule(dynamic, 64)
+    for (int64_t i = 0; i < n; i++) {
+        const int32_t y = (int32_t)(i / w), x = (int32_t)(i % w);
+        int64_t q = row_ptr[i];
+        for (int32_t dy = -rw; dy <= rw; dy++) {
+            for (int32_t dx = -rw; dx <= rw; dx++) {
+                const int32_t yj = y + dy, xj = x + dx;
+                if ((dy == 0 && dx == 0) || yj < 0 || yj >= h || xj < 0 || xj >= w) continue;
+                double s = 0.0;
+                for (int32_t a = -rp; a <= rp; a++) {
+                    for (int32_t b = -rp; b <= rp; b++) {
+                        int32_t yi2 = y + a, xi2 = x + b, yj2 = yj + a, xj2 = xj + b;
+                        yi2 = yi2 < 0 ? 0 : (yi2 >= h ? h - 1 : yi2);
+                        xi2 = xi2 < 0 ? 0 : (xi2 >= w ? w - 1 : xi2);
+                        yj2 = yj2 < 0 ? 0 : (yj2 >= h ? h - 1 : yj2);
+                        xj2 = xj2 < 0 ? 0 : (xj2 >= w ? w - 1 : xj2);
+                        const double *ci = img + ((int64_t)yi2 * w + xi2) * C;
+                        const double *cj = img + ((int64_t)yj2 * w + xj2) * C;
+                        double d2 = 0.0;
+                        for (int32_t c = 0; c < C; c++) d2 += (ci[c] - cj[c]) * (ci[c] - cj[c]);
+                        s += alpha[(a + rp) * P + (b + rp)] * d2;
+                    }
+                }
+                col[q] = (int32_t)((int64_t)yj * w + xj);
+                wout[q] = exp(-s * inv_s2);
+                q++;
+            }
+        }
+    }
+    return row_ptr[n];
+}
+
 int glo_num_threads(void)
 {
 #ifdef _OPENMP

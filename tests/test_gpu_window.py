@@ -211,6 +211,42 @@ def test_solve_parity(h, w, rw, store, tol):
     assert np.all(np.diff(eg[:, 0]) <= 1e-6 * np.abs(eg).max())
 
 
+@pytest.mark.timeout(900)
+@pytest.mark.parametrize("store,tol", [(("f32", "f32"), 1e-5), (("bf16", "f32"), 2e-2)])
+def test_solve_512_window25(store, tol):
+    """A whole solve on a 512 x 512 image with the paper's 25 x 25 window and
+    5 x 5 patches (160 M stored edges; the graph of the C oracle, pinned to the
+    definition), 10 DCA steps x 4 damped-Jacobi sweeps, against the float64
+    oracle."""
+    key = ("w512",)
+    if key not in _CACHE:
+        p = window_problem(512, 512, 12, 2, seed=5)
+        _CACHE[key] = (p, c_oracle.window_graph(_oracle_image(p), p.rw, p.rp, p.sigma))
+    p, (rp_, col, ww) = _CACHE[key]
+    say(f"window solve 512x512 r=12 store={store}: {len(col)} edges")
+    op = _op(p, store[0])
+    assert op.info()["nnz"] == len(col)
+    U = torch.from_numpy(np.ascontiguousarray(p.u0)).to(DEV, DT[store[1]]).contiguous()
+    st = op.solve(torch.from_numpy(p.labels).to(DEV), U, eps=p.eps, c=p.c, eta=p.eta,
+                  precond=p.precond, outer=p.outer, sweeps=p.sweeps, delta0=p.delta0)
+    Ug = U.to(torch.float64).cpu().numpy()
+    eg, _, flag = gl.split_stats(st.cpu(), 1, p.outer, p.sweeps)
+    key2 = ("w512-oracle",)
+    if key2 not in _CACHE:
+        _CACHE[key2] = c_oracle.dca_solve(p.n, rp_, col, ww, p.labels, p.u0, eps=p.eps, c=p.c,
+                                          eta=p.eta, precond=p.precond, outer=p.outer,
+                                          sweeps=p.sweeps, delta0=p.delta0)
+    Uo, eo, _ = _CACHE[key2]
+    err = float(np.abs(Ug - Uo).max())
+    agree, decided = _decided_agreement(Ug, Uo, tol)
+    e_rel = float(np.abs(eg.numpy() - eo).max() / np.abs(eo).max())
+    say(f"  max|dU| {err:.3e}  agreement {agree:.6f} on {decided:.4f} decided  energy rel {e_rel:.2e}")
+    assert flag == 0.0
+    assert err <= tol
+    assert agree >= 0.999 and decided >= 0.5
+    assert e_rel <= (1e-4 if store == ("f32", "f32") else 2e-2)
+
+
 @pytest.mark.parametrize("precond", ["perturbed_jacobi", "richardson"])
 def test_solve_other_preconditioners(precond):
     p, _ = _problem(40, 150, 5)

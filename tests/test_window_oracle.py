@@ -98,3 +98,16 @@ def test_window_rows_match_full_graph():
         np.testing.assert_allclose(wij, ww[rp_[i]:rp_[i + 1]], rtol=1e-13)
         assert di == pytest.approx(d[i], rel=1e-13)
         np.testing.assert_allclose(dj, d[js], rtol=1e-13)
+
+
+@pytest.mark.parametrize("h,w,rw,rp", [(13, 70, 3, 2), (40, 37, 5, 1), (9, 20, 4, 0), (1, 30, 3, 2),
+                                        (30, 1, 2, 1)])
+def test_c_window_graph_matches_definition(h, w, rw, rp):
+    # the plain C window graph (used at 512 x 512 and above) against the
+    # numpy one written from the definition: same structure, weights to rounding
+    from oracle import c_oracle
+    img = np.random.default_rng(h * 1000 + w).uniform(0.0, 255.0, (h, w, 3))
+    a = wo.window_graph(img, rw, rp, 40.0)
+    b = c_oracle.window_graph(img, rw, rp, 40.0)
+    assert np.array_equal(a[0], b[0]) and np.array_equal(a[1], b[1])
+    assert np.abs(a[2] - b[2]).max() <= 1e-13 * a[2].max()
