@@ -35,6 +35,7 @@ DSIZE = {"f64": 8, "f32": 4, "bf16": 2, "f16": 2}
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_sweep_image2048_k4_traffic.json")
 # sources whose change invalidates recorded counter traffic of the sweep kernel
 WINDOW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_sweep_1024_r12_traffic.json")  # + _<weights>
+HBM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_sweep_image4096_k4_traffic.json")  # + _<weights>
 TRAFFIC_SOURCES = ["gl_grid.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
                    "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_grid_f16.hip",
                    "gl_unit_grid_bf16.hip", "gl_unit_grid_f32.hip", "gl_window.hpp"]
@@ -532,9 +533,11 @@ def hbm_scale_bench(dev, reps):
         t_create = time.perf_counter() - t1
         _, lam = op.power_max_eig(x0, 150)
         U = torch.from_numpy(p.u0).to(dev, gl.TORCH_DTYPES[su]).contiguous()
-        sweep_ms = gl.time_sweeps(op, labels, U, eps=p.eps, c=p.c, eta=p.eta, precond=p.precond,
-                                  delta0=p.delta0, lambda_max=lam, step_k=p.step_k, reps=reps)
+        # the solves first: the sweep timing starts on a busy GPU, as in a solve
         wall, _, _ = timed_solves(op, labels, U.clone(), p, lam, 3, 1)
+        sweep_ms = min(gl.time_sweeps(op, labels, U, eps=p.eps, c=p.c, eta=p.eta,
+                                      precond=p.precond, delta0=p.delta0, lambda_max=lam,
+                                      step_k=p.step_k, reps=reps) for _ in range(3))
         info = op.info()
         B = sweep_bytes(info, p.n, p.K, su)
         Bm = method_bytes(info, p.n, p.K, sw, su)
@@ -545,7 +548,9 @@ def hbm_scale_bench(dev, reps):
             "frac_of_hbm_peak": B / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "frac_method": Bm / (sweep_ms * 1e-3) / 1e9 / HBM_PEAK_GBPS,
             "solves_per_s": 3 / wall, "ms_per_solve": wall / 3 * 1e3,
-            "operator_create_ms": t_create * 1e3, "stored_entries": info["stored_entries"]}
+            "operator_create_ms": t_create * 1e3, "stored_entries": info["stored_entries"],
+            "traffic": recorded_traffic(p.name, f"{sw}/{su}",
+                                        HBM_TRAFFIC_FILE.replace(".json", f"_{sw}.json"))}
         log(f"  {sw}/{su}: {B / 1e9:.2f} GB per sweep in {sweep_ms * 1e3:.1f} us "
             f"({out[f'{sw}/{su}']['sweep_gbps']:.0f} GB/s), {wall / 3 * 1e3:.1f} ms per solve")
         op.close()
