@@ -157,6 +157,62 @@ def test_large_requests_multi_pass():
         assert err <= 2e-2 and agree >= 0.999
 
 
+def _hub_problem(n=6000, hubs=11, K=4, seed=17):
+    """A ring with `hubs` hub rows joined to 300-2 000 random nodes each (more
+    than 8 heavy rows, so their workgroups are padded to 16), as a served
+    request: symmetric CSR, 3 % labels."""
+    from synth.graphs import Graph
+    rng = np.random.default_rng(seed)
+    edges = {}
+    for i in range(n):
+        j = (i + 1) % n
+        edges[(min(i, j), max(i, j))] = 0.5
+    for h in range(hubs):
+        for j in rng.choice(np.arange(hubs, n), int(rng.integers(300, 2000)), replace=False):
+            edges[(h, int(j))] = float(rng.uniform(0.1, 1.0))
+    rows = np.array([a for a, b in edges] + [b for a, b in edges])
+    cols = np.array([b for a, b in edges] + [a for a, b in edges])
+    ww = np.array(list(edges.values()) * 2)
+    order = np.lexsort((cols, rows))
+    rows, cols, ww = rows[order], cols[order], ww[order]
+    rp = np.zeros(n + 1, dtype=np.int64)
+    np.cumsum(np.bincount(rows, minlength=n), out=rp[1:])
+    g = Graph(n, torch.from_numpy(rp), torch.from_numpy(cols.astype(np.int32)), torch.from_numpy(ww))
+    labels = np.full(n, -1, dtype=np.int32)
+    pick = rng.choice(n, n * 3 // 100, replace=False)
+    labels[pick] = rng.integers(0, K, pick.size)
+    u0 = np.where(labels[:, None] >= 0, -1.0, 0.0) * np.ones((1, K))
+    u0[labels >= 0, labels[labels >= 0]] = 1.0
+    q = type("P", (), {})()
+    q.graph, q.n, q.K, q.labels, q.u0 = g, n, K, labels, u0.astype(np.float32)
+    q.eps, q.c, q.eta, q.precond, q.outer, q.sweeps, q.delta0 = 100.0, 11.0, 100.0, "damped_jacobi", 20, 4, 1e-6
+    return q
+
+
+def test_heavy_rows_served_equal_alone():
+    """Hub rows go to workgroups of their own (rows longer than 16 G): the
+    served result is still bitwise gl_solve's, beside an ordinary request."""
+    hub = _hub_problem()
+    other = served(*MIX[0])
+    srv = gl.Server(512 << 20, max_slots=4, store_w="bf16", store_u="bf16")
+    try:
+        t_hub, t_other = submit(srv, hub), submit(srv, other)
+        r_hub, r_other = srv.poll(t_hub), srv.poll(t_other)
+    finally:
+        srv.close()
+    op = gl.Operator(hub.graph.row_ptr.to(DEV), hub.graph.col.to(DEV), hub.graph.weight.to(DEV),
+                     store_w="bf16", layout="direct")
+    deg = np.diff(hub.graph.row_ptr.numpy())
+    assert (deg > 16 * op.info()["lanes_per_row"]).sum() > 8
+    op.close()
+    assert_same_as_alone(r_hub, alone(hub, "bf16", "bf16"), "hub request")
+    assert_same_as_alone(r_other, alone(other, "bf16", "bf16"), "ordinary request")
+    Uo = oracle(hub)[0]
+    err = float(np.abs(r_hub["U"] - Uo).max())
+    say(f"  hub request: max|U - oracle| {err:.3e}")
+    assert err <= 2e-2 and label_agreement(r_hub["U"], Uo) >= 0.999
+
+
 def test_budget_serialises_admission():
     """An arena that holds one request at a time still serves all of them, in
     order, with the same results; a request above the budget is refused."""
