@@ -20,7 +20,7 @@ import torch
 import paper_2303_14495_amd as gl
 from synth.configs import StreamItem, served_problem
 from tests.gpu_helpers import DEV, label_agreement, say
-from oracle import c_oracle
+from oracle import c_oracle, precision
 
 pytestmark = pytest.mark.gpu
 
@@ -189,12 +189,22 @@ def _hub_problem(n=6000, hubs=11, K=4, seed=17):
     return q
 
 
-def test_heavy_rows_served_equal_alone():
+@pytest.mark.parametrize("store_u", ["bf16", "f16"])
+def test_heavy_rows_served_equal_alone(store_u):
     """Hub rows go to workgroups of their own (rows longer than 16 G): the
-    served result is still bitwise gl_solve's, beside an ordinary request."""
+    served result is still bitwise gl_solve's, beside an ordinary request.
+
+    Against the oracle the bar is 2e-2 or twice the rounding floor of this
+    graph, whichever is larger: the floor is the float64 oracle's distance
+    from the same steps run with bf16 weights, the field rounded to its
+    storage type and float32 arithmetic (oracle.precision).  On this ring the
+    hubs reach |u| = 3.3, where one bf16 step is 1.6e-2, and many ring nodes
+    sit near u = 0 far from any label, so bf16 field storage alone moves the
+    result by 4.4e-2 and flips 0.5 % of the argmax labels; f16 storage stays
+    within 3.5e-3."""
     hub = _hub_problem()
     other = served(*MIX[0])
-    srv = gl.Server(512 << 20, max_slots=4, store_w="bf16", store_u="bf16")
+    srv = gl.Server(512 << 20, max_slots=4, store_w="bf16", store_u=store_u)
     try:
         t_hub, t_other = submit(srv, hub), submit(srv, other)
         r_hub, r_other = srv.poll(t_hub), srv.poll(t_other)
@@ -205,12 +215,20 @@ def test_heavy_rows_served_equal_alone():
     deg = np.diff(hub.graph.row_ptr.numpy())
     assert (deg > 16 * op.info()["lanes_per_row"]).sum() > 8
     op.close()
-    assert_same_as_alone(r_hub, alone(hub, "bf16", "bf16"), "hub request")
-    assert_same_as_alone(r_other, alone(other, "bf16", "bf16"), "ordinary request")
+    assert_same_as_alone(r_hub, alone(hub, "bf16", store_u), "hub request")
+    assert_same_as_alone(r_other, alone(other, "bf16", store_u), "ordinary request")
     Uo = oracle(hub)[0]
+    rp, col, w = hub.graph.numpy()
+    kw = params(hub)
+    Ur = precision.dca_solve_rounded(hub.n, rp, col, w, hub.labels, hub.u0, store_w="bf16",
+                                     store_u=store_u, **kw)
+    floor = precision.gap(Ur, Uo, hub.n, rp, col, w, hub.labels, hub.eps, hub.eta)
     err = float(np.abs(r_hub["U"] - Uo).max())
-    say(f"  hub request: max|U - oracle| {err:.3e}")
-    assert err <= 2e-2 and label_agreement(r_hub["U"], Uo) >= 0.999
+    agree = label_agreement(r_hub["U"], Uo)
+    say(f"  hub request ({store_u} field): max|U - oracle| {err:.3e} (floor "
+        f"{floor['max_abs_dU']:.3e}), labels {agree:.6f} (floor {floor['label_agreement']:.6f})")
+    assert err <= max(2e-2, 2.0 * floor["max_abs_dU"])
+    assert agree >= min(0.999, floor["label_agreement"] - 0.002)
 
 
 def test_budget_serialises_admission():
