@@ -505,13 +505,13 @@ gl_status gl_server_destroy(gl_server *srv);
  * list that cannot be filled ends with index -1 and distance +inf.
  * d > 64 (wide features, e.g. 784 pixels): the same result, found through
  * the matrix cores: <x_i, x_j> of the centred points rounded to f16 (scaled
- * by a power of two) by a rocBLAS GEMM with f32 accumulation, in chunks of at
- * most 2 GiB of f32 products; per query the 64 best approximate distances
- * become candidates whose exact distances are recomputed, and a
+ * by a power of two), f32 accumulation, in one fused kernel that filters
+ * every block of products into per-query candidate lists without storing
+ * them; per query 64 candidates get their exact distances recomputed, and a
  * certificate from the rounding-error bound proves that no other point can
  * enter or tie the k best; queries without it are rescanned exactly
  * (gl_knn_fallback_rows).  Non-finite coordinates are rejected
- * (GL_E_INVALID_ARG).  Allocates about n (2 d + 8) bytes plus the chunk as
+ * (GL_E_INVALID_ARG).  Allocates about n (2 d + 300) bytes as
  * stream-ordered temporaries and synchronises `stream`.
  * Errors: GL_E_INVALID_ARG, GL_E_NOMEM, GL_E_HIP. */
 gl_status gl_knn(const float *x, int64_t n, int32_t d, int32_t k, int32_t *idx_out,
