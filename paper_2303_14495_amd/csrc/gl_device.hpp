@@ -35,6 +35,23 @@ template <typename A> __device__ __forceinline__ A cvt(bf16 x) {
     return (A)__uint_as_float((uint32_t)x.bits << 16);
 }
 
+// The value of a 16-bit load, opaque to the optimizer from here on, so that
+// its conversion to the accumulator type stays where the value is used:
+// moved up next to the load, the conversion would bring the wait for that load
+// ahead of later requests.  Wider types need no conversion.
+__device__ __forceinline__ float late(float x) { return x; }
+__device__ __forceinline__ double late(double x) { return x; }
+__device__ __forceinline__ f16 late(f16 x) {
+    uint32_t b = __builtin_bit_cast(uint16_t, x);
+    asm volatile("" : "+v"(b));
+    return __builtin_bit_cast(f16, (uint16_t)b);
+}
+__device__ __forceinline__ bf16 late(bf16 x) {
+    uint32_t b = x.bits;
+    asm volatile("" : "+v"(b));
+    return bf16{(uint16_t)b};
+}
+
 template <typename T> struct store_as;
 template <> struct store_as<double> {
     static __device__ __forceinline__ double from(double x) { return x; }
@@ -154,6 +171,16 @@ __device__ __forceinline__ A pick(const A (&z)[K], int k) {
 #pragma unroll
     for (int i = 1; i < K; ++i) r = (k == i) ? z[i] : r;
     return r;
+}
+
+// The same pointer, known to address global memory: a pointer read from memory
+// (rather than passed as a kernel argument) is otherwise accessed with flat
+// instructions, and every wait for a flat load waits for all outstanding
+// loads and LDS operations alike.  The round trip through the global address
+// space lets the compiler's address-space inference use global loads.
+template <typename T> __device__ __forceinline__ T* as_global(T* p) {
+    typedef __attribute__((address_space(1))) T* G;
+    return (T*)(G)(uintptr_t)p;
 }
 
 // Hardware dispatch hands consecutive workgroup ids round-robin to the 8 XCDs.

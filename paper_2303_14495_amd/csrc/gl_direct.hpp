@@ -136,9 +136,12 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, in
         const bool live = row < a.g.n && !(heavy_min >= 0 && end[t] - beg[t] > heavy_min);
         const int64_t node = live ? (a.order ? (int64_t)a.order[row] : row) : 0;
         int32_t lab = -1;
-        A dl = (A)1, u[CPL], v[CPL];
+        A dl = (A)1;
+        // own-row inputs as stored: converted only after the gathers are
+        // issued, so that their loads are in flight together
+        TU ur[CPL], vr[CPL];
 #pragma unroll
-        for (int c = 0; c < CPL; ++c) u[c] = v[c] = (A)0;
+        for (int c = 0; c < CPL; ++c) ur[c] = vr[c] = store_as<TU>::from((A)0);
         if (live) {
             lab = a.labels[node];
             if (a.dd) dl = a.dd[node];
@@ -146,8 +149,8 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, in
             for (int c = 0; c < CPL; ++c) {
                 const int k = q + c * G;
                 if (k < K) {
-                    u[c] = cvt<A>(a.ut[node * K + k]);
-                    v[c] = cvt<A>(a.vin[node * K + k]);
+                    ur[c] = a.ut[node * K + k];
+                    vr[c] = a.vin[node * K + k];
                 }
             }
         }
@@ -163,7 +166,9 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, in
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
                 const int k = q + c * G;
-                if (k < K) update_column<K>(a, node, k, lab, dl, u[c], v[c], pick<K>(z, k), e_acc[c], r_acc[c]);
+                if (k < K)
+                    update_column<K>(a, node, k, lab, dl, cvt<A>(late(ur[c])), cvt<A>(late(vr[c])), pick<K>(z, k),
+                                     e_acc[c], r_acc[c]);
             }
         }
     }

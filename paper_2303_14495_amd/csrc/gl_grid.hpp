@@ -316,14 +316,20 @@ __device__ __forceinline__ void grid_sweep_body(const GridSweepArgs<TU, typename
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     int32_t lab = -1;
     A dl = (A)1;
-    A uu[K], e_acc[K], r_acc[K];
+    A e_acc[K], r_acc[K];
+    // u^t as stored: converted at the update, so that its load does not hold
+    // back the chunk requests issued after it
+    TU ur[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) uu[k] = e_acc[k] = r_acc[k] = (A)0;
+    for (int k = 0; k < K; ++k) {
+        e_acc[k] = r_acc[k] = (A)0;
+        ur[k] = store_as<TU>::from((A)0);
+    }
     auto prefetch = [&](bool ok, int64_t p) {
         if (!ok) return;
         lab = a.labels[p];
         if (a.dd) dl = a.dd[p];
-        load_row<K>(a.ut + p * K, uu);
+        load_raw<K>(a.ut + p * K, ur);
     };
     auto finish = [&](bool ok, int64_t p, const A (&z)[K], const A (&vc)[K]) {
         if (!ok) return;
@@ -332,7 +338,7 @@ __device__ __forceinline__ void grid_sweep_body(const GridSweepArgs<TU, typename
         TU vnew[K];
 #pragma unroll
         for (int k = 0; k < K; ++k) {
-            const A zk = z[k], u = uu[k], v = vc[k];
+            const A zk = z[k], u = cvt<A>(ur[k]), v = vc[k];
             const A y = lab < 0 ? (A)0 : (K == 1 ? (lab == 1 ? (A)1 : (A)-1) : (lab == k ? (A)1 : (A)-1));
             const A rhs = a.k.c * u - (u * u * u - u) * a.k.inv_eps + a.k.eta * lam * y;
             const A lv = a.dd ? dl * v - zk : v - zk;

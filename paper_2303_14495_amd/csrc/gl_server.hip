@@ -63,16 +63,17 @@ struct ServedDesc {
 template <typename TW, typename TU>
 __device__ __forceinline__ SweepArgs<TW, TU, int32_t> served_args(const ServedDesc& d) {
     SweepArgs<TW, TU, int32_t> a;
-    a.rp = d.rp;
-    a.col = d.col;
-    a.w = static_cast<const TW*>(d.w);
-    a.ut = static_cast<const TU*>(d.ut);
-    a.vin = static_cast<const TU*>(d.vin);
-    a.vout = static_cast<TU*>(d.vout);
-    a.labels = d.labels;
+    // every array of a descriptor is device memory of the arena
+    a.rp = as_global(d.rp);
+    a.col = as_global(d.col);
+    a.w = as_global(static_cast<const TW*>(d.w));
+    a.ut = as_global(static_cast<const TU*>(d.ut));
+    a.vin = as_global(static_cast<const TU*>(d.vin));
+    a.vout = d.vout ? as_global(static_cast<TU*>(d.vout)) : nullptr;
+    a.labels = as_global(d.labels);
     a.order = nullptr;
     a.dd = nullptr;  // served solves use L_s
-    a.partials = static_cast<float*>(d.partials);
+    a.partials = d.partials ? as_global(static_cast<float*>(d.partials)) : nullptr;
     a.g = RowGeom{d.n, d.rows_per_block, d.G, d.log2G, d.tiles, 0};
     a.energy = d.energy;
     a.k.eps = d.coef[0];
@@ -87,7 +88,7 @@ __device__ __forceinline__ SweepArgs<TW, TU, int32_t> served_args(const ServedDe
     a.k.alpha = d.coef[9];
     a.k.kappa = d.coef[10];
     a.k.ga = a.k.gd = a.k.gl = 0.f;
-    a.heavy = d.heavy;
+    a.heavy = d.heavy ? as_global(d.heavy) : nullptr;
     a.nheavy = d.nheavy;
     a.hblocks = d.hblocks;
     return a;
