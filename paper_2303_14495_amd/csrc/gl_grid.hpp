@@ -32,7 +32,7 @@ constexpr int kGridTX = 64;                       // tile width: one wavefront p
 constexpr int kGridTY = 8;                        // tile height: eight wavefronts
 constexpr int kGridThreads = kGridTX * kGridTY;   // 512
 constexpr int kGridR = 7;                         // window radius (15 x 15)
-constexpr int kGridS = kGridTX + 2 * kGridR;      // staged row length, 78
+constexpr int kGridS = kGridTX + 2 * kGridR + 2;  // staged row length, 80: image columns 64 tx - 8 .. 64 tx + 71
 constexpr int kGridHY = kGridTY + 2 * kGridR;     // staged rows, 22
 constexpr int kGridCells = kGridS * kGridHY;      // 1716
 constexpr int kGridChunk = 8;                     // entries per chunk
@@ -167,26 +167,31 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     }
 
     // stage V over the tile and its halo, in two halves around the first
-    // chunk fetch: every lane issues the loads of its 4 cells at once (before
-    // waiting for its chunk count), and writes them to LDS afterwards, cells
-    // outside the image zeroed.  Loads use 32-bit byte offsets from the first
-    // image row of the halo (the host keeps 22 rows of V below 2^32 bytes); a
-    // cell outside the image loads that row's first pixel, a valid address.
-    static_assert(4 * kGridThreads >= kGridCells, "one staging pass");
-    const int gx0 = tx * kGridTX - kGridR, gy0 = ty * kGridTY - kGridR;
+    // chunk fetch: lane t < 440 issues the loads of cells t % 20 + 20 u,
+    // u = 0..3, of staged row t / 20 at once (before waiting for its chunk
+    // count; neighbouring lanes take neighbouring cells), and writes them to
+    // LDS afterwards, cells outside the image zeroed.  Loads use
+    // 32-bit byte offsets from the first image row of the halo (the host keeps
+    // 22 rows of V below 2^32 bytes); a cell outside the image loads that
+    // row's first pixel, a valid address.
+    constexpr int kSL = kGridS / 4;  // lanes per staged row, 4 cells each
+    static_assert(kSL * kGridHY <= kGridThreads && kGridS % 4 == 0, "one staging pass");
+    const int gx0 = tx * kGridTX - kGridR - 1, gy0 = ty * kGridTY - kGridR;
     const int gyb = gy0 < 0 ? 0 : gy0;
     const unsigned char* vb = reinterpret_cast<const unsigned char*>(V + (int64_t)gyb * op.width * K);
+    const bool stager = (int)threadIdx.x < kSL * kGridHY;
+    const int shy = (int)threadIdx.x / kSL, shx = (int)threadIdx.x - shy * kSL;
+    const int sgy = gy0 + shy;
+    const bool row_in = stager && (unsigned)sgy < (unsigned)op.height;
+    // row distance <= 21 and width < 2^24 (host checks): 24-bit multiply
+    const uint32_t rowcell = row_in ? __umul24((uint32_t)(sgy - gyb), (uint32_t)op.width) : 0u;
     L vals[4][K];
     bool in[4];
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
-        const int c = u * kGridThreads + (int)threadIdx.x;
-        const int cc = c < kGridCells ? c : kGridCells - 1;
-        const int hy = cc / kGridS, hx = cc - hy * kGridS;
-        const int gy = gy0 + hy, gx = gx0 + hx;
-        in[u] = (unsigned)gy < (unsigned)op.height && (unsigned)gx < (unsigned)op.width;
-        // row distance <= 21 and width < 2^24 (host checks): 24-bit multiply
-        const uint32_t cell = in[u] ? __umul24((uint32_t)(gy - gyb), (uint32_t)op.width) + (uint32_t)gx : 0u;
+        const int gx = gx0 + shx + kSL * u;
+        in[u] = row_in && (unsigned)gx < (unsigned)op.width;
+        const uint32_t cell = in[u] ? rowcell + (uint32_t)gx : 0u;
         const TU* src = reinterpret_cast<const TU*>(vb + cell * (uint32_t)(K * sizeof(TU)));
         if constexpr (sizeof(L) == sizeof(TU)) {
             load_raw<K>(src, vals[u]);
@@ -196,7 +201,7 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     }
 
     const int maxc = wave_max_nonneg(cnt);
-    const int rowbase = wave * kGridS + lane;  // staged cell of window offset (-7, -7)
+    const int rowbase = wave * kGridS + lane + 1;  // staged cell of window offset (-7, -7)
     constexpr int kCB = K * (int)sizeof(L);    // bytes per staged cell
     // tiles beyond 64 KB (wide fields, e.g. 16 float columns) keep the 32-bit
     // offset decode
@@ -236,10 +241,10 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
     };
     fetch(0);
 
+    if (stager) {
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
-        const int c = u * kGridThreads + (int)threadIdx.x;
-        if (c < kGridCells) {
+        for (int u = 0; u < 4; ++u) {
+            const int c = shy * kGridS + shx + kSL * u;
             if constexpr ((K * sizeof(L)) % 4 == 0) {
                 // select whole words: all-zero bits are +0 in every field type
                 uint32_t wv[K * sizeof(L) / 4];
@@ -284,7 +289,7 @@ __device__ __forceinline__ void grid_products(const GridOp& op, const TU* __rest
             }
         }
     }
-    const int center = (wave + kGridR) * kGridS + lane + kGridR;
+    const int center = (wave + kGridR) * kGridS + lane + kGridR + 1;
     A vc[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) vc[k] = cvt<A>(hv[center * K + k]);
