@@ -218,6 +218,24 @@ def test_knn_wide_matches_oracle(n, d, k):
     assert np.abs(d2 - ref).max() <= 1e-6 * max(1.0, float(ref.max()))
 
 
+@pytest.mark.parametrize("n,d,k", [(40, 70, 5), (129, 65, 12), (300, 128, 13), (1100, 192, 8)])
+def test_knn_wide_block_edges(n, d, k):
+    """Shapes at the edges of the fused kernel's blocking: fewer points than
+    one 128-point block (one query block, a partial point block), one point
+    past a block, d a multiple of the 64-coordinate staging step (no padding),
+    and k on both sides of the switch between eight lists of 8 (k <= 12) and
+    two lists of 32 candidates per query."""
+    x = mixture(n, d, seed=n + d + k)
+    say(f"wide knn edges n={n} d={d} k={k}")
+    idx, d2 = gl.knn(torch.from_numpy(x).to(DEV), k)
+    fb = gl.knn_fallback_rows()
+    idx, d2 = idx.cpu().numpy(), d2.cpu().numpy()
+    check(x, k, idx, d2, np.arange(n))
+    say(f"  exact rescans {fb}")
+    ref = _exact_f32(x, np.arange(n), idx)
+    assert np.abs(d2 - ref).max() <= 1e-6 * max(1.0, float(ref.max()))
+
+
 def test_knn_wide_ties_use_the_exact_rescan():
     """The 96 unit vectors of R^96 are all at squared distance 2 from each
     other: every candidate ties with points outside the 64 candidates, so
