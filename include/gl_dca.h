@@ -217,14 +217,19 @@ typedef struct gl_window_graph {
 /* Build the operator of a window graph on the device, with implicit columns
  * (layout GL_LAYOUT_WINDOW): the weights are computed in F64 once, the degrees
  * d_i summed in F64 in increasing neighbour order, and the stored weights
- * (what_ij for L_s, w_ij for L, rounded to `store_w`) kept for each pixel and
- * window offset; neighbours outside the image store 0.  Sweeps stream
- * (2r+1)^2 - 1 weights per pixel and no column indices.  The operator serves
- * gl_solve, gl_laplacian_apply, gl_power_max_eig, gl_second_eigenpair and
- * gl_time_sweeps like any other; one call with K columns needs
- * K * (64 + 2r) * (4 + 2r) * (4 or 8 bytes) <= 147456 of LDS, checked per
- * call (GL_E_INVALID_ARG).  Construction holds 8 bytes per stored entry of
- * temporary device memory.  Synchronises `stream`.  Errors: GL_E_INVALID_ARG,
+ * (what_ij for L_s, w_ij for L, rounded to `store_w`) kept once per pair: each
+ * pixel keeps the first half of its window in scan order (dy < 0, or dy = 0
+ * and dx < 0), and W being symmetric, the other half is its neighbours';
+ * neighbours outside the image store 0.  Sweeps stream ((2r+1)^2 - 1) / 2
+ * weights per pixel and no column indices.  The operator serves gl_solve,
+ * gl_laplacian_apply, gl_power_max_eig, gl_second_eigenpair and gl_time_sweeps
+ * like any other; their workspace sizes include the per-tile region sums of
+ * one product (about (4 + r)(64 + 2r) / 256 x K x (4 or 8) bytes per pixel),
+ * and gl_laplacian_apply takes that buffer from the stream-ordered allocator
+ * for the call.  One call with K columns needs
+ * 2 K * (64 + 2r) * (4 + r) * (4 or 8 bytes) <= 147456 of LDS, checked per
+ * call (GL_E_INVALID_ARG).  Construction holds 8 bytes per pixel and window
+ * offset of temporary device memory.  Synchronises `stream`.  Errors: GL_E_INVALID_ARG,
  * GL_E_BAD_GRAPH (a pixel whose weights all underflow to zero: a degree of
  * 0), GL_E_DTYPE, GL_E_NOMEM, GL_E_HIP. */
 gl_status gl_window_operator_create(const gl_window_graph *graph, gl_dtype store_w, void *stream,
@@ -247,7 +252,9 @@ gl_status gl_operator_layout(const gl_operator *op, int32_t *layout, int64_t *st
                              int32_t *halo_max, int64_t *halo_total, int64_t *stream_bytes);
 
 /* Y = L_s X = X - D^{-1/2} W D^{-1/2} X (Section 2.2) for device X, Y of
- * n x K elements of `dtype` (1 <= K <= 16); X and Y must not overlap. */
+ * n x K elements of `dtype` (1 <= K <= 16); X and Y must not overlap.  On a
+ * renumbered operator and on the window layout the call allocates its scratch
+ * from the stream-ordered allocator (hipMallocAsync) and frees it on `stream`. */
 gl_status gl_laplacian_apply(const gl_operator *op, int32_t K, gl_dtype dtype,
                              const void *X, void *Y, void *stream);
 

@@ -86,7 +86,6 @@ gl::RowLaunch gl::operator_rows(const gl_operator* op) {
         return r;
     }
     if (op->layout == gl::LAYOUT_WINDOW) {
-        r.woff = op->woff;
         r.wheight = op->wheight;
         r.wwidth = op->wwidth;
         r.wr = op->wr;
@@ -135,7 +134,8 @@ bool pair_ok(gl_dtype w, gl_dtype u) {
     return dtype_size(w) != 0 && dtype_size(u) != 0;
 }
 
-// The window layout stages K columns of its tile's halo in LDS.
+// The window layout stages K columns of V and of the accumulator over its
+// tile's region in LDS.
 gl_status window_fits(const gl_operator* op, int K, gl_dtype u) {
     if (op->layout == gl::LAYOUT_GRID) {
         const size_t need = (size_t)K * gl::kGridCells * (u == GL_F64 ? 8 : u == GL_F32 ? 4 : 2);
@@ -280,7 +280,6 @@ void free_op(gl_operator* op) {
     (void)hipFree(op->w);
     (void)hipFree(op->degree);
     (void)hipFree(op->dd);
-    (void)hipFree(op->woff);
     (void)hipFree(op->goffs);
     (void)hipFree(op->gwbase);
     (void)hipFree(op->gcnt);
@@ -812,13 +811,13 @@ gl_status gl_operator_layout(const gl_operator* op, int32_t* layout, int64_t* st
         return GL_OK;
     }
     if (op->layout == gl::LAYOUT_WINDOW) {
-        const int64_t cells = (int64_t)(gl::kWinTX + 2 * op->wr) * (gl::kWinTY + 2 * op->wr);
+        const int64_t cells = gl::window_region(op->wr);
         if (layout) *layout = GL_LAYOUT_WINDOW;
         if (stored) *stored = op->stored;
         if (halo_max) *halo_max = (int32_t)cells;
         if (halo_total) *halo_total = cells * op->nblocks;
         if (stream_bytes)
-            *stream_bytes = op->stored * (int64_t)dtype_size(op->store_w) + (int64_t)op->wM * 4 +
+            *stream_bytes = op->stored * (int64_t)dtype_size(op->store_w) +
                             (op->dd ? op->n * (op->store_w == GL_F64 ? 8 : 4) : 0);
         return GL_OK;
     }
@@ -846,6 +845,17 @@ gl_status gl_laplacian_apply(const gl_operator* op, int32_t K, gl_dtype dtype, c
     const char *x = (const char*)X, *y = (const char*)Y;
     if (x < y + bytes && y < x + bytes) return fail(GL_E_INVALID_ARG, "X and Y overlap");
     hipStream_t s = (hipStream_t)stream;
+    if (op->layout == gl::LAYOUT_WINDOW) {
+        // region sums of the window product (stream-ordered scratch)
+        gl::RowLaunch r = row_launch(op);
+        GL_HIP(hipMallocAsync(&r.wpart, gl::window_part_bytes(op, K, dtype == GL_F64 ? 8 : 4), s),
+               "laplacian scratch");
+        const hipError_t e = launch_laplacian(dtype, K, r, X, Y, s);
+        const hipError_t ef = hipFreeAsync(r.wpart, s);
+        GL_HIP(e, "laplacian launch");
+        GL_HIP(ef, "laplacian scratch");
+        return GL_OK;
+    }
     if (!op->order) {
         GL_HIP(launch_laplacian(dtype, K, row_launch(op), X, Y, s), "laplacian launch");
         return GL_OK;
@@ -868,7 +878,8 @@ gl_status gl_laplacian_apply(const gl_operator* op, int32_t K, gl_dtype dtype, c
 gl_status gl_power_workspace_size(const gl_operator* op, size_t* bytes) {
     if (!gl::valid(op) || !bytes) return fail(GL_E_INVALID_ARG, "operator (a live operator handle) and bytes must not be NULL");
     const gl::RowLaunch r = row_launch(op);
-    *bytes = (op->order ? 3 : 2) * align256((size_t)op->n * 4) + align256((size_t)2 * r.grid * 4) + 256;
+    *bytes = (op->order ? 3 : 2) * align256((size_t)op->n * 4) + align256((size_t)2 * r.grid * 4) + 256 +
+             align256(gl::window_part_bytes(op, 1, 4));
     return GL_OK;
 }
 
@@ -891,9 +902,10 @@ gl_status gl_power_max_eig(const gl_operator* op, int32_t iters, const float* x0
     char* tail = (char*)partials + align256((size_t)2 * r.grid * 4);
     float* scale = (float*)tail;
     double* sums = (double*)(tail + 64);
+    float* wpart = (float*)(tail + 256);  // window layout: region sums of one product
 
     auto pass = [&](const float* x, float* y, int mode, const float* sc) -> hipError_t {
-        if (op->layout == gl::LAYOUT_WINDOW) return gl::launch_window_power(op, x, y, mode, sc, partials, s);
+        if (op->layout == gl::LAYOUT_WINDOW) return gl::launch_window_power(op, x, y, mode, sc, partials, wpart, s);
         if (op->layout == gl::LAYOUT_GRID) {
             gl::GridPowerArgs a;
             a.op.w = op->w;
@@ -1012,8 +1024,10 @@ gl_status gl_solve_workspace_size(const gl_operator* op, int32_t K, gl_dtype sto
     const size_t acc = store_u == GL_F64 ? 8 : 4;
     // ordered operators keep all three field buffers and the labels in position order
     // the block partial sums of up to kStatGroup sweeps wait for one reduction
+    // the window layout's region sums of one product
     *bytes = (op->order ? 3 * field + align256((size_t)op->n * 4) : 2 * field) +
-             (size_t)gl::kStatGroup * align256((size_t)2 * K * gl::sweep_grid(r) * acc);
+             (size_t)gl::kStatGroup * align256((size_t)2 * K * gl::sweep_grid(r) * acc) +
+             align256(gl::window_part_bytes(op, K, acc));
     return GL_OK;
 }
 
@@ -1082,6 +1096,8 @@ gl_status solve_impl(const gl_operator* op, const gl_params* params, int32_t K, 
 
     gl::SweepLaunch L;
     L.r = row_launch(op);
+    // the window layout's region sums sit at the end of the workspace
+    L.r.wpart = (char*)ws + (need - align256(gl::window_part_bytes(op, K, store_u == GL_F64 ? 8 : 4)));
     L.labels = labels;
     L.partials = stats ? partials : nullptr;
     const double g0 = precond_g(p.precond, 0.0, p), g1 = precond_g(p.precond, 1.0, p);
@@ -1192,6 +1208,8 @@ gl_status gl_time_sweeps(const gl_operator* op, const gl_params* params, int32_t
     char* Q = (char*)ws + field;
     gl::SweepLaunch L;
     L.r = row_launch(op);
+    // the window layout's region sums sit at the end of the workspace
+    L.r.wpart = (char*)ws + (need - align256(gl::window_part_bytes(op, K, store_u == GL_F64 ? 8 : 4)));
     L.labels = labels;
     L.partials = (char*)ws + 2 * field;
     L.energy = 0;

@@ -138,6 +138,7 @@ struct EigWs {
     double* partials = nullptr;  // [(m + 2) * nb]
     double* dots = nullptr;      // [m + 2]
     double* y = nullptr;         // [m]
+    float* wpart = nullptr;      // window layout: region sums of one product
     size_t bytes = 0;
 };
 
@@ -159,6 +160,7 @@ EigWs carve(const gl_operator* op, int32_t m, char* base) {
     e.partials = (double*)take((size_t)(m + 2) * e.nb * 8);
     e.dots = (double*)take((size_t)(m + 2) * 8);
     e.y = (double*)take((size_t)m * 8);
+    e.wpart = (float*)take(gl::window_part_bytes(op, 1, 4));
     e.bytes = o;
     return e;
 }
@@ -258,7 +260,8 @@ gl_status gl_second_eigenpair(const gl_operator* op, int32_t krylov, int32_t max
     hipStream_t s = (hipStream_t)stream;
     const int64_t n = op->n;
     const unsigned g256 = (unsigned)((n + 255) / 256);
-    const gl::RowLaunch rows = gl::operator_rows(op);
+    gl::RowLaunch rows = gl::operator_rows(op);
+    rows.wpart = e.wpart;
     hipError_t err = hipSuccess;
 #define GE_CHECK(what)                                                                  \
     do {                                                                                \

@@ -36,8 +36,9 @@ struct RowLaunch {
     const int32_t* halo;
     const int32_t* hp;
     int32_t hmax;
-    // window layout (implicit columns of an image's search window)
-    const int32_t* woff;
+    // window layout (implicit columns of an image's search window); wpart: the
+    // caller's buffer for the region sums of one product (window_part_bytes)
+    void* wpart;
     int32_t wheight, wwidth, wr, wM, wtiles_x;
     // grid layout (window-relative one-byte columns); image size and tiles_x
     // share wheight, wwidth, wtiles_x
@@ -88,9 +89,8 @@ struct gl_operator {
     int32_t* heavy = nullptr;  // direct layout: rows longer than 16 G, in position order
     int32_t nheavy = 0;
     // window layout: image height x width, window radius, offsets per pixel,
-    // tiles per image row, LDS offset of every window offset
+    // tiles per image row
     int32_t wheight = 0, wwidth = 0, wr = 0, wM = 0, wtiles_x = 0;
-    int32_t* woff = nullptr;
     // grid layout: offset bytes, first chunk per row segment, chunks per pixel
     // (image size and tiles per row in wheight, wwidth, wtiles_x)
     uint64_t* goffs = nullptr;
@@ -118,9 +118,10 @@ inline int64_t sweep_grid(const RowLaunch& r) {
     return r.grid + (r.layout == LAYOUT_DIRECT ? ((int64_t)r.nheavy + 7) / 8 * 8 : 0);
 }
 
-// Power-method pass on the window layout (see gl::window_power_kernel).
+// Power-method pass on the window layout (see gl::window_power_kernel); part:
+// window_part_bytes(op, 1, 4) bytes.
 hipError_t launch_window_power(const gl_operator* op, const float* x, float* y, int mode, const float* scale,
-                               float* partials, hipStream_t s);
+                               float* partials, float* part, hipStream_t s);
 
 // gl_knn for 64 < d <= 4096 (arguments checked by the caller); *fallback_rows
 // receives the number of rows recomputed by the exact scan.
@@ -129,6 +130,10 @@ gl_status knn_wide(const float* x, int64_t n, int32_t d, int32_t k, int32_t* idx
 
 // LDS bytes one window-layout block needs for K columns of accumulator size acc.
 size_t window_lds_bytes(const gl_operator* op, int K, size_t acc);
+
+// Bytes of the region-sum buffer of one window product with K columns of
+// accumulator size acc (0 for other layouts).
+size_t window_part_bytes(const gl_operator* op, int K, size_t acc);
 
 // Thread-local message returned by gl_last_error().
 void set_last_error(const std::string& msg);

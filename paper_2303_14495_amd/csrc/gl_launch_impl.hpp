@@ -119,7 +119,6 @@ static hipError_t tile_laplacian_k(int K, const RowLaunch& r, const void* x, voi
 static WinOp window_op(const RowLaunch& r) {
     WinOp op;
     op.w = r.w;
-    op.woff = r.woff;
     op.height = r.wheight;
     op.width = r.wwidth;
     op.r = r.wr;
@@ -128,15 +127,31 @@ static WinOp window_op(const RowLaunch& r) {
     return op;
 }
 
+// LDS of window_part_kernel: V and the accumulator over one tile's region.
 static size_t window_lds(const RowLaunch& r, int K, size_t acc) {
-    return (size_t)K * (kWinTX + 2 * r.wr) * (kWinTY + 2 * r.wr) * acc;
+    return 2 * (size_t)K * window_region(r.wr) * acc;
+}
+
+// Region sums of W X over every tile into r.wpart (the first pass of each
+// window product).
+template <int K, typename TW, typename TU>
+static void window_part_launch(const RowLaunch& r, const void* x, hipStream_t s) {
+    typedef typename acc_of<TU>::type A;
+    WinPartArgs<TU> a;
+    a.op = window_op(r);
+    a.v = static_cast<const TU*>(x);
+    a.part = static_cast<A*>(r.wpart);
+    hipLaunchKernelGGL((window_part_kernel<K, TW, TU>), dim3((unsigned)r.grid), dim3(256), window_lds(r, K, sizeof(A)),
+                       s, a);
 }
 
 template <typename TW, typename TU>
 static hipError_t window_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
     typedef typename acc_of<TU>::type A;
+    if (!L.r.wpart) return hipErrorInvalidValue;
     WinSweepArgs<TU, A> a;
     a.op = window_op(L.r);
+    a.part = static_cast<const A*>(L.r.wpart);
     a.ut = static_cast<const TU*>(L.ut);
     a.vin = static_cast<const TU*>(L.vin);
     a.vout = static_cast<TU*>(L.vout);
@@ -146,11 +161,11 @@ static hipError_t window_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
     a.energy = L.energy;
     a.k = make_sweep_args<TW, TU, int32_t>(L).k;
     const dim3 grid((unsigned)L.r.grid), block(256);
-    const size_t lds = window_lds(L.r, K, sizeof(A));
     switch (K) {
-#define GL_CASE(KK)                                                                         \
-    case KK:                                                                                \
-        hipLaunchKernelGGL((window_sweep_kernel<KK, TW, TU>), grid, block, lds, s, a);     \
+#define GL_CASE(KK)                                                                 \
+    case KK:                                                                        \
+        window_part_launch<KK, TW, TU>(L.r, L.vin, s);                              \
+        hipLaunchKernelGGL((window_sweep_kernel<KK, TW, TU>), grid, block, 0, s, a); \
         break;
         GL_K_CASES(GL_CASE)
 #undef GL_CASE
@@ -163,17 +178,19 @@ static hipError_t window_sweep_k(int K, const SweepLaunch& L, hipStream_t s) {
 template <typename TW, typename TU>
 static hipError_t window_laplacian_k(int K, const RowLaunch& r, const void* x, void* y, hipStream_t s) {
     typedef typename acc_of<TU>::type A;
+    if (!r.wpart) return hipErrorInvalidValue;
     WinLapArgs<TU> a;
     a.op = window_op(r);
+    a.part = static_cast<const A*>(r.wpart);
     a.x = static_cast<const TU*>(x);
     a.y = static_cast<TU*>(y);
     a.dd = static_cast<const A*>(r.dd);
     const dim3 grid((unsigned)r.grid), block(256);
-    const size_t lds = window_lds(r, K, sizeof(A));
     switch (K) {
-#define GL_CASE(KK)                                                                          \
-    case KK:                                                                                 \
-        hipLaunchKernelGGL((window_laplacian_kernel<KK, TW, TU>), grid, block, lds, s, a);  \
+#define GL_CASE(KK)                                                                     \
+    case KK:                                                                            \
+        window_part_launch<KK, TW, TU>(r, x, s);                                        \
+        hipLaunchKernelGGL((window_laplacian_kernel<KK, TW, TU>), grid, block, 0, s, a); \
         break;
         GL_K_CASES(GL_CASE)
 #undef GL_CASE

@@ -92,7 +92,8 @@ __global__ __launch_bounds__(256) void window_degree_kernel(const double* __rest
 }
 
 // Stored weights: what_pq = w_pq / sqrt(d_p d_q) (raw = 0) or w_pq (raw != 0),
-// rounded once to TW; one block per (tile, group of GS offsets).
+// rounded once to TW, for the first half of each pixel's window; one block per
+// (tile, vector of GS offsets).
 template <typename TW>
 __global__ __launch_bounds__(256) void window_fill_kernel(const double* __restrict__ raw,
                                                           const double* __restrict__ d, int32_t h, int32_t w,
@@ -100,7 +101,7 @@ __global__ __launch_bounds__(256) void window_fill_kernel(const double* __restri
                                                           u32x4* __restrict__ out) {
     constexpr int GS = 16 / (int)sizeof(TW);
     const int64_t b = blockIdx.x;
-    const int g = blockIdx.y, ng = M / GS;
+    const int g = blockIdx.y, ng = window_groups(M, GS);
     const int side = 2 * r + 1;
     const int ty = (int)(b / tiles_x), tx = (int)(b - (int64_t)ty * tiles_x);
     const int x = tx * kWinTX + (threadIdx.x & 63), y = ty * kWinTY + (threadIdx.x >> 6);
@@ -110,13 +111,14 @@ __global__ __launch_bounds__(256) void window_fill_kernel(const double* __restri
 #pragma unroll
     for (int e = 0; e < GS; ++e) {
         const int m = g * GS + e;
-        const double wv = raw[(b * M + m) * 256 + threadIdx.x];
         double o = 0.0;
-        if (ok && wv != 0.0) {
-            const int cell = m < M / 2 ? m : m + 1;
-            const int dy = cell / side - r, dx = cell - (cell / side) * side - r;
-            const double dq = d[(int64_t)(y + dy) * w + (x + dx)];
-            o = raw_mode ? wv : wv / (sqrt(dp) * sqrt(dq));
+        if (m < M / 2) {
+            const double wv = raw[(b * M + m) * 256 + threadIdx.x];
+            if (ok && wv != 0.0) {
+                const int dy = m / side - r, dx = m - (m / side) * side - r;  // the cell index of the scan equals m
+                const double dq = d[(int64_t)(y + dy) * w + (x + dx)];
+                o = raw_mode ? wv : wv / (sqrt(dp) * sqrt(dq));
+            }
         }
         vals[e] = store_as<TW>::from(o);
     }
@@ -125,27 +127,42 @@ __global__ __launch_bounds__(256) void window_fill_kernel(const double* __restri
     out[(b * ng + g) * 256 + threadIdx.x] = v;
 }
 
-// Unnormalized L: diagonal dd_p = sum of p's stored weights (double, offset
-// order), rounded to the accumulator type A.
+// Unnormalized L: diagonal dd_p = sum of the stored weights of p's whole window
+// (double, offset order: the first half from p's vectors, the second half
+// from the neighbours', which keep the weight of the mirrored offset),
+// rounded to the accumulator type A.
 template <typename TW, typename A>
 __global__ __launch_bounds__(256) void window_rowsum_kernel(const TW* __restrict__ wst, int32_t h, int32_t w,
-                                                            int32_t tiles_x, int32_t M, A* __restrict__ dd) {
+                                                            int32_t r, int32_t tiles_x, int32_t M,
+                                                            A* __restrict__ dd) {
     constexpr int GS = 16 / (int)sizeof(TW);
     const int64_t b = blockIdx.x;
     const int ty = (int)(b / tiles_x), tx = (int)(b - (int64_t)ty * tiles_x);
     const int x = tx * kWinTX + (threadIdx.x & 63), y = ty * kWinTY + (threadIdx.x >> 6);
     if (x >= w || y >= h) return;
-    const int ng = M / GS;
+    const int ng = window_groups(M, GS), side = 2 * r + 1;
+    auto stored = [&](int qy, int qx, int m) {
+        const int64_t qb = (int64_t)(qy / kWinTY) * tiles_x + qx / kWinTX;
+        const int ql = (qy % kWinTY) * kWinTX + qx % kWinTX;
+        return cvt<double>(wst[((qb * ng + m / GS) * 256 + ql) * GS + m % GS]);
+    };
     double s = 0.0;
-    for (int g = 0; g < ng; ++g)
-        for (int e = 0; e < GS; ++e) s += cvt<double>(wst[((b * ng + g) * 256 + threadIdx.x) * GS + e]);
+    for (int m = 0; m < M; ++m) {
+        if (m < M / 2) {
+            s += stored(y, x, m);
+        } else {
+            const int cell = m + 1;
+            const int qy = y + cell / side - r, qx = x + cell % side - r;
+            if (qy < h && qx >= 0 && qx < w) s += stored(qy, qx, M - 1 - m);
+        }
+    }
     dd[(int64_t)y * w + x] = (A)s;
 }
 
 template <typename TW>
 hipError_t launch_fill_t(const double* raw, const double* d, const gl_operator* op, int raw_mode, hipStream_t s) {
     const int GS = 16 / (int)sizeof(TW);
-    const dim3 grid((unsigned)op->nblocks, (unsigned)(op->wM / GS));
+    const dim3 grid((unsigned)op->nblocks, (unsigned)window_groups(op->wM, GS));
     hipLaunchKernelGGL(window_fill_kernel<TW>, grid, dim3(256), 0, s, raw, d, op->wheight, op->wwidth, op->wr,
                        op->wtiles_x, op->wM, raw_mode, (u32x4*)op->w);
     return hipGetLastError();
@@ -154,7 +171,7 @@ hipError_t launch_fill_t(const double* raw, const double* d, const gl_operator* 
 template <typename TW, typename A>
 hipError_t launch_rowsum_t(const gl_operator* op, hipStream_t s) {
     hipLaunchKernelGGL((window_rowsum_kernel<TW, A>), dim3((unsigned)op->nblocks), dim3(256), 0, s,
-                       (const TW*)op->w, op->wheight, op->wwidth, op->wtiles_x, op->wM, (A*)op->dd);
+                       (const TW*)op->w, op->wheight, op->wwidth, op->wr, op->wtiles_x, op->wM, (A*)op->dd);
     return hipGetLastError();
 }
 
@@ -176,31 +193,45 @@ gl_status wfail(gl_status st, const std::string& msg) {
 }  // namespace
 
 size_t window_lds_bytes(const gl_operator* op, int K, size_t acc) {
-    return (size_t)K * (kWinTX + 2 * op->wr) * (kWinTY + 2 * op->wr) * acc;
+    return 2 * (size_t)K * window_region(op->wr) * acc;
+}
+
+size_t window_part_bytes(const gl_operator* op, int K, size_t acc) {
+    if (op->layout != LAYOUT_WINDOW) return 0;
+    return (size_t)op->nblocks * window_region(op->wr) * K * acc;
+}
+
+template <typename TW>
+static void window_power_t(const WinPowerArgs& a, const gl_operator* op, hipStream_t s) {
+    WinPartArgs<float> pa;
+    pa.op = a.op;
+    pa.v = a.x;
+    pa.part = const_cast<float*>(a.part);
+    const dim3 grid((unsigned)op->nblocks), block(256);
+    hipLaunchKernelGGL((window_part_kernel<1, TW, float>), grid, block, window_lds_bytes(op, 1, 4), s, pa);
+    hipLaunchKernelGGL(window_power_kernel<TW>, grid, block, 0, s, a);
 }
 
 hipError_t launch_window_power(const gl_operator* op, const float* x, float* y, int mode, const float* scale,
-                               float* partials, hipStream_t s) {
+                               float* partials, float* part, hipStream_t s) {
     WinPowerArgs a;
     a.op.w = op->w;
-    a.op.woff = op->woff;
     a.op.height = op->wheight;
     a.op.width = op->wwidth;
     a.op.r = op->wr;
     a.op.M = op->wM;
     a.op.tiles_x = op->wtiles_x;
+    a.part = part;
     a.x = x;
     a.y = y;
     a.scale = scale;
     a.partials = partials;
     a.dd = (const float*)op->dd;
     a.mode = mode;
-    const size_t lds = window_lds_bytes(op, 1, 4);
-    const dim3 grid((unsigned)op->nblocks), block(256);
     switch (op->store_w) {
-        case GL_F32: hipLaunchKernelGGL(window_power_kernel<float>, grid, block, lds, s, a); break;
-        case GL_BF16: hipLaunchKernelGGL(window_power_kernel<bf16>, grid, block, lds, s, a); break;
-        case GL_F16: hipLaunchKernelGGL(window_power_kernel<f16>, grid, block, lds, s, a); break;
+        case GL_F32: window_power_t<float>(a, op, s); break;
+        case GL_BF16: window_power_t<bf16>(a, op, s); break;
+        case GL_F16: window_power_t<f16>(a, op, s); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
@@ -234,7 +265,9 @@ extern "C" gl_status gl_window_operator_create(const gl_window_graph* g, gl_dtyp
     const int32_t tiles_x = (w + kWinTX - 1) / kWinTX, tiles_y = (h + kWinTY - 1) / kWinTY;
     const int64_t ntiles = (int64_t)tiles_x * tiles_y;
     const int64_t n = (int64_t)h * w;
-    const int64_t stored = ntiles * 256 * M;
+    const int GS = 16 / (int)wdtype_size(store_w);
+    const int64_t stored = ntiles * 256 * window_groups(M, GS) * GS;  // first half of each window, padded
+    const int64_t rawn = ntiles * 256 * M;                             // F64 weights of the whole windows
 
     gl_operator* op = new gl_operator();
     op->n = n;
@@ -256,13 +289,6 @@ extern "C" gl_status gl_window_operator_create(const gl_window_graph* g, gl_dtyp
     op->nnz = sy * sx - n;
     (void)hipGetDevice(&op->device);
 
-    // offsets in scan order, the centre skipped, as LDS offsets of the staged tile
-    const int32_t S = kWinTX + 2 * r;
-    std::vector<int32_t> woff(M);
-    for (int32_t m = 0; m < M; ++m) {
-        const int32_t cell = m < M / 2 ? m : m + 1;
-        woff[m] = (cell / side - r) * S + (cell % side - r);
-    }
     // patch weights: separable Gaussian normalised to sum 1
     WinAlpha al = {};
     {
@@ -284,10 +310,9 @@ extern "C" gl_status gl_window_operator_create(const gl_window_graph* g, gl_dtyp
     int32_t* flags = nullptr;
     std::string what;
     hipError_t e = hipMalloc(&op->w, wbytes);
-    if (e == hipSuccess) e = hipMalloc((void**)&op->woff, (size_t)M * 4);
     if (e == hipSuccess) e = hipMalloc((void**)&op->degree, (size_t)n * 8);
     if (e == hipSuccess) e = hipMalloc((void**)&J, Jn * sizeof(float4));
-    if (e == hipSuccess) e = hipMalloc((void**)&raw, (size_t)stored * 8);
+    if (e == hipSuccess) e = hipMalloc((void**)&raw, (size_t)rawn * 8);
     if (e == hipSuccess) e = hipMalloc((void**)&flags, 16);
     if (e != hipSuccess) {
         (void)hipFree(J);
@@ -297,15 +322,14 @@ extern "C" gl_status gl_window_operator_create(const gl_window_graph* g, gl_dtyp
         (void)hipGetLastError();
         return wfail(GL_E_NOMEM, "device allocation for the window operator failed");
     }
-    op->bytes = wbytes + (size_t)M * 4 + (size_t)n * 8;
+    op->bytes = wbytes + (size_t)n * 8;
     unsigned long long* first_bad = (unsigned long long*)(flags + 2);
     const unsigned long long none = ~0ull;
     int32_t hflags[4] = {0, 0, 0, 0};
     __builtin_memcpy(&hflags[2], &none, 8);
 
-    e = hipMemcpyAsync(op->woff, woff.data(), (size_t)M * 4, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemcpyAsync(flags, hflags, 16, hipMemcpyHostToDevice, s);
-    if (e == hipSuccess) e = hipMemsetAsync(raw, 0, (size_t)stored * 8, s);
+    e = hipMemcpyAsync(flags, hflags, 16, hipMemcpyHostToDevice, s);
+    if (e == hipSuccess) e = hipMemsetAsync(raw, 0, (size_t)rawn * 8, s);
     if (e == hipSuccess) {
         hipLaunchKernelGGL(window_pad_kernel, dim3((unsigned)((Jn + 255) / 256)), dim3(256), 0, s, g->image, h, w,
                            g->channels, rp, J);

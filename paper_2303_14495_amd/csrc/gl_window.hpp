@@ -2,23 +2,35 @@
 //
 // Pixel i is joined to every pixel j of its (2r+1) x (2r+1) search window
 // (the proximity term N_s), j != i.  The neighbour at window offset o = (dy, dx)
-// is pixel i + dy * width + dx, so no column index is stored: a sweep streams
-// only the weights, one value per (pixel, offset), which is 2 bytes per
-// nonzero in BF16/F16 against 6 for a CSR row with 32-bit columns.
+// is pixel i + dy * width + dx, so no column index is stored.  W is symmetric,
+// and each pair is stored once: pixel i keeps the weights of the first half of
+// its window in scan order (row-major over (dy, dx)), the Mh = M / 2 offsets
+// with dy < 0, or dy = 0 and dx < 0 (M = (2r+1)^2 - 1); the weight of (i, j)
+// for an offset of the second half is the one j keeps for the offset -o.  A
+// sweep streams Mh weights per pixel, 1 byte per nonzero in BF16/F16 against
+// 6 for a CSR row with 32-bit columns.
 //
 // Work mapping: a block of 256 lanes owns a 64 x 4 pixel tile, one pixel per
-// lane and one image row per wavefront.  The block stages V over the tile and
-// its r-wide halo in LDS (zeros outside the image), then every lane walks the
-// M = (2r+1)^2 - 1 offsets of its pixel in scan order (row-major over (dy, dx),
-// the centre skipped).  Its weights for GS consecutive offsets form one
-// 16-byte vector, and the vectors of the block's 256 pixels are contiguous, so
-// each wavefront load reads 1 KB in one piece:
-//     w[((tile * (M / GS) + g) * 256 + lane) * GS + e]   (offset m = g * GS + e).
-// The LDS reads of one wavefront are 64 consecutive words of one halo row,
-// free of bank conflicts for every offset.  Offsets whose neighbour falls
-// outside the image, and pixels of a ragged tile outside it, store weight 0.
-// Each lane sums its row in a fixed order (two interleaved partial sums added
-// at the end), so results are bitwise reproducible.
+// lane and one image row per wavefront, and a region of (4 + r) x (64 + 2r)
+// cells: the tile, the r image rows above it and r columns on each side.  The
+// block stages V over the region in LDS (zeros outside the image), then every
+// lane walks the Mh stored offsets of its pixel in scan order.  For the stored
+// weight w of (i, i + o) it adds w V[i + o] to its own sum (a register) and
+// w V[i] to the cell of i + o (an LDS accumulator over the region), so each
+// weight is read once and used in both directions.  The offsets of one window
+// row (one dy) form a phase, and the block synchronises between phases: the
+// four wavefronts then add into four different image rows, and every cell
+// receives its contributions in a fixed order.  The block writes the region
+// (its own pixels' sums included) to a partial buffer, and the consumer kernel
+// sums, for each pixel, the regions of the tiles that cover it, in a fixed
+// order: (W V)_i is bitwise reproducible.
+//
+// Stored weights: GS = 16 / sizeof(weight) consecutive offsets of one pixel
+// form one 16-byte vector, and the vectors of a tile's 256 pixels are
+// contiguous, so each wavefront load reads 1 KB in one piece:
+//     w[((tile * NG + g) * 256 + lane) * GS + e]   (offset m = g * GS + e < Mh),
+// NG = ceil(Mh / GS), padding zero.  Offsets whose neighbour falls outside the
+// image, and pixels of a ragged tile outside it, store weight 0.
 #pragma once
 
 #include "gl_kernels.hpp"
@@ -32,31 +44,40 @@ constexpr int kWinMaxRp = 4;  // largest patch radius (9 x 9 patch)
 constexpr size_t kWinLdsMax = 147456;  // LDS one block may stage (the device allows 160 KB; room for static LDS)
 
 struct WinOp {
-    const void* w;          // weights, layout above
-    const int32_t* woff;    // [M] LDS offset dy * S + dx of window offset m
+    const void* w;          // stored weights, layout above
     int32_t height, width;  // image
     int32_t r;              // window radius
     int32_t M;              // offsets per pixel, (2r+1)^2 - 1
     int32_t tiles_x;        // tiles per image row
 };
 
-// Z = W V for the pixel of this lane (W: the stored weights, normalized for
-// L_s or raw for L); also returns the pixel's own V row from the staged tile.
-//   prefetch(ok, p): issue the loads of the pixel's own data
-//   finish(ok, p, z, v): consume the product
-template <int K, typename TW, typename TU, typename A, typename Pre, typename Fin>
-__device__ __forceinline__ void window_products(const WinOp& op, const TU* __restrict__ V, int64_t b, A* hv,
-                                                Pre&& prefetch, Fin&& finish) {
+// Cells of one tile's region: (4 + r) rows of 64 + 2r.
+__host__ __device__ __forceinline__ int window_region(int r) { return (kWinTY + r) * (kWinTX + 2 * r); }
+
+// Stored vectors per pixel for GS offsets per vector.
+__host__ __device__ __forceinline__ int window_groups(int M, int GS) { return (M / 2 + GS - 1) / GS; }
+
+template <typename TU> struct WinPartArgs {
+    WinOp op;
+    const TU* v;                          // V, n x K
+    typename acc_of<TU>::type* part;      // [tile][region cell][K]
+};
+
+// First pass of every window product: the region sums of one tile (above).
+template <int K, typename TW, typename TU>
+__global__ __launch_bounds__(256) void window_part_kernel(WinPartArgs<TU> a) {
+    typedef typename acc_of<TU>::type A;
     constexpr int GS = 16 / (int)sizeof(TW);
-    const int S = kWinTX + 2 * op.r, HY = kWinTY + 2 * op.r, plane = S * HY;
+    extern __shared__ unsigned char smem_raw[];
+    const WinOp& op = a.op;
+    const int S = kWinTX + 2 * op.r, plane = window_region(op.r);
+    A* hv = reinterpret_cast<A*>(smem_raw);  // V over the region, [k][cell]
+    A* acc = hv + K * plane;                 // contributions to the region's cells, [k][cell]
+    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int ty = (int)(b / op.tiles_x), tx = (int)(b - (int64_t)ty * op.tiles_x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
-    const int x = tx * kWinTX + lane, y = ty * kWinTY + wave;
-    const bool ok = x < op.width && y < op.height;
-    const int64_t p = (int64_t)y * op.width + x;
-    prefetch(ok, p);
 
-    // stage V over the tile and its halo, kStage cells per lane in flight
+    // stage V over the region, kStage cells per lane in flight; clear the accumulator
     constexpr int kStage = 4;
     const int gx0 = tx * kWinTX - op.r, gy0 = ty * kWinTY - op.r;
     const float invS = 1.0f / (float)S;
@@ -72,7 +93,7 @@ __device__ __forceinline__ void window_products(const WinOp& op, const TU* __res
             const int gy = gy0 + hy, gx = gx0 + (c - hy * S);
             cell[u] = c;
             if (c < plane && gy >= 0 && gy < op.height && gx >= 0 && gx < op.width) {
-                load_row<K>(V + ((int64_t)gy * op.width + gx) * K, vals[u]);
+                load_row<K>(a.v + ((int64_t)gy * op.width + gx) * K, vals[u]);
             } else {
 #pragma unroll
                 for (int k = 0; k < K; ++k) vals[u][k] = (A)0;
@@ -82,47 +103,118 @@ __device__ __forceinline__ void window_products(const WinOp& op, const TU* __res
         for (int u = 0; u < kStage; ++u) {
             if (cell[u] < plane) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) hv[k * plane + cell[u]] = vals[u][k];
+                for (int k = 0; k < K; ++k) {
+                    hv[k * plane + cell[u]] = vals[u][k];
+                    acc[k * plane + cell[u]] = (A)0;
+                }
             }
         }
     }
     __syncthreads();
 
-    const int base = (wave + op.r) * S + lane + op.r;
-    const int ng = op.M / GS;
+    const int base = (wave + op.r) * S + lane + op.r;  // the lane's own cell
+    A vp[K];
+#pragma unroll
+    for (int k = 0; k < K; ++k) vp[k] = hv[k * plane + base];
+    const int ng = window_groups(op.M, GS), mh = op.M / 2, side = 2 * op.r + 1;
     const u32x4* wp = static_cast<const u32x4*>(op.w) + b * (int64_t)ng * 256 + threadIdx.x;
     A z0[K], z1[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) z0[k] = z1[k] = (A)0;
-#pragma unroll 4
-    for (int g = 0; g < ng; ++g) {
-        // streamed once per sweep: a non-temporal load keeps the weights from
-        // evicting the V halos that neighbouring tiles re-read from L2
-        const u32x4 wq = __builtin_nontemporal_load(wp + (int64_t)g * 256);
+    // offset m of the first half: window row `row` and column `col` (dy = row - r,
+    // dx = col - r), i.e. the cell vbase + row * S + col
+    const int vbase = wave * S + lane;
+    int m = 0, row = 0, col = 0;
+    auto ld = [&](int g) { return __builtin_nontemporal_load(wp + (int64_t)(g < ng ? g : ng - 1) * 256); };
+    auto step = [&](const u32x4& wq) {
         TW we[GS];
         __builtin_memcpy(we, &wq, 16);
 #pragma unroll
         for (int e = 0; e < GS; ++e) {
-            const int at = base + op.woff[g * GS + e];
-            const A wv = cvt<A>(we[e]);
+            // past the last offset (the padding of the last vectors and the
+            // vectors loaded ahead of the end): weight 0 at the own cell
+            const bool live = m < mh;
+            const int at = live ? vbase + row * S + col : base;
+            const A wv = live ? cvt<A>(we[e]) : (A)0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
                 if (e & 1) z1[k] += wv * hv[k * plane + at];
                 else z0[k] += wv * hv[k * plane + at];
+                acc[k * plane + at] += wv * vp[k];
+            }
+            ++m;
+            if (++col == side) {  // end of a phase: one window row done by all four wavefronts
+                col = 0;
+                ++row;
+                __syncthreads();
             }
         }
+    };
+    u32x4 w0 = ld(0), w1 = ld(1), w2 = ld(2), w3 = ld(3);
+    for (int g = 0; g < ng; g += 4) {
+        step(w0);
+        w0 = ld(g + 4);
+        step(w1);
+        w1 = ld(g + 5);
+        step(w2);
+        w2 = ld(g + 6);
+        step(w3);
+        w3 = ld(g + 7);
     }
-    A z[K], vc[K];
+    __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) {
-        z[k] = z0[k] + z1[k];
-        vc[k] = hv[k * plane + base];
+    for (int k = 0; k < K; ++k) acc[k * plane + base] += z0[k] + z1[k];
+    __syncthreads();
+    A* out = a.part + b * (int64_t)plane * K;
+    for (int i = threadIdx.x; i < plane * K; i += 256) {
+        const int c = i / K, k = i - c * K;
+        out[i] = acc[k * plane + c];
     }
-    finish(ok, p, z, vc);
+}
+
+// (W V) at pixel (y, x): the sum of the regions of the tiles that cover it
+// (tile rows from the pixel's own down, columns left to right).
+template <int K, typename A>
+__device__ __forceinline__ void window_gather(const WinOp& op, const A* __restrict__ part, int y, int x, A (&z)[K]) {
+    const int S = kWinTX + 2 * op.r, plane = window_region(op.r);
+    const int tiles_y = (op.height + kWinTY - 1) / kWinTY;
+    const int ty = y / kWinTY, tx = x / kWinTX;
+#pragma unroll
+    for (int k = 0; k < K; ++k) z[k] = (A)0;
+    const int ty1 = min(tiles_y - 1, (y + op.r) / kWinTY);
+    for (int t2 = ty; t2 <= ty1; ++t2) {
+        const int ry = y - (t2 * kWinTY - op.r);
+        for (int t3 = tx - 1; t3 <= tx + 1; ++t3) {
+            const int rx = x - (t3 * kWinTX - op.r);
+            if (t3 < 0 || t3 >= op.tiles_x || rx < 0 || rx >= S) continue;
+            const A* src = part + ((int64_t)(t2 * op.tiles_x + t3) * plane + ry * S + rx) * K;
+#pragma unroll
+            for (int k = 0; k < K; ++k) z[k] += src[k];
+        }
+    }
+}
+
+// The pixel of this lane in the second pass (same tiles and block order as the first).
+struct WinPixel {
+    int64_t b, p;
+    int y, x;
+    bool ok;
+};
+
+__device__ __forceinline__ WinPixel window_pixel(const WinOp& op) {
+    WinPixel q;
+    q.b = xcd_remap(blockIdx.x, gridDim.x);
+    const int ty = (int)(q.b / op.tiles_x), tx = (int)(q.b - (int64_t)ty * op.tiles_x);
+    q.x = tx * kWinTX + (int)(threadIdx.x & 63);
+    q.y = ty * kWinTY + (int)(threadIdx.x >> 6);
+    q.ok = q.x < op.width && q.y < op.height;
+    q.p = (int64_t)q.y * op.width + q.x;
+    return q;
 }
 
 template <typename TU, typename A> struct WinSweepArgs {
     WinOp op;
+    const A* part;  // region sums of W vin (window_part_kernel)
     const TU* ut;
     const TU* vin;
     TU* vout;  // nullptr: energy-only pass
@@ -133,27 +225,24 @@ template <typename TU, typename A> struct WinSweepArgs {
     SweepCoef<A> k;
 };
 
-// One sweep (or the energy-only pass) on the window layout; the update is the
-// one of sweep_block, for all K columns of the lane's pixel.
+// One sweep (or the energy-only pass) on the window layout, after
+// window_part_kernel over vin; the update is the one of sweep_block, for all K
+// columns of the lane's pixel.
 template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(256) void window_sweep_kernel(WinSweepArgs<TU, typename acc_of<TU>::type> a) {
     typedef typename acc_of<TU>::type A;
-    extern __shared__ unsigned char smem_raw[];
-    A* hv = reinterpret_cast<A*>(smem_raw);
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    int32_t lab = -1;
-    A dl = (A)1;
-    A uu[K], e_acc[K], r_acc[K];
+    const WinPixel q = window_pixel(a.op);
+    A e_acc[K], r_acc[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) uu[k] = e_acc[k] = r_acc[k] = (A)0;
-    auto prefetch = [&](bool ok, int64_t p) {
-        if (!ok) return;
-        lab = a.labels[p];
-        if (a.dd) dl = a.dd[p];
+    for (int k = 0; k < K; ++k) e_acc[k] = r_acc[k] = (A)0;
+    if (q.ok) {
+        const int64_t p = q.p;
+        const int32_t lab = a.labels[p];
+        const A dl = a.dd ? a.dd[p] : (A)1;
+        A uu[K], vc[K], z[K];
         load_row<K>(a.ut + p * K, uu);
-    };
-    auto finish = [&](bool ok, int64_t p, const A (&z)[K], const A (&vc)[K]) {
-        if (!ok) return;
+        load_row<K>(a.vin + p * K, vc);
+        window_gather<K, A>(a.op, a.part, q.y, q.x, z);
         const A lam = lab >= 0 ? (A)1 : (A)0;
         const A ginv = a.dd ? (A)1 / (a.k.ga + a.k.gd * dl + a.k.gl * lam) : (lab >= 0 ? a.k.ginv1 : a.k.ginv0);
         TU vnew[K];
@@ -174,14 +263,15 @@ __global__ __launch_bounds__(256) void window_sweep_kernel(WinSweepArgs<TU, type
             }
         }
         if (a.vout) store_raw<K>(a.vout + p * K, vnew);
-    };
-    window_products<K, TW, TU, A>(a.op, a.vin, b, hv, prefetch, finish);
-    if (a.partials) block_stats<K, K>(e_acc, r_acc, 1, a.partials, (int64_t)gridDim.x, b);
+    }
+    if (a.partials) block_stats<K, K>(e_acc, r_acc, 1, a.partials, (int64_t)gridDim.x, q.b);
 }
 
-// Y = X - What X (L_s X) or D X - W X (L X) on the window layout
+// Y = X - What X (L_s X) or D X - W X (L X) on the window layout, after
+// window_part_kernel over X.
 template <typename TU> struct WinLapArgs {
     WinOp op;
+    const typename acc_of<TU>::type* part;
     const TU* x;
     TU* y;
     const typename acc_of<TU>::type* dd;
@@ -190,24 +280,21 @@ template <typename TU> struct WinLapArgs {
 template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(256) void window_laplacian_kernel(WinLapArgs<TU> a) {
     typedef typename acc_of<TU>::type A;
-    extern __shared__ unsigned char smem_raw[];
-    A* hv = reinterpret_cast<A*>(smem_raw);
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
-    A dl = (A)1;
-    auto prefetch = [&](bool ok, int64_t p) {
-        if (ok && a.dd) dl = a.dd[p];
-    };
-    auto finish = [&](bool ok, int64_t p, const A (&z)[K], const A (&vc)[K]) {
-        if (!ok) return;
+    const WinPixel q = window_pixel(a.op);
+    if (!q.ok) return;
+    const A dl = a.dd ? a.dd[q.p] : (A)1;
+    A vc[K], z[K];
+    load_row<K>(a.x + q.p * K, vc);
+    window_gather<K, A>(a.op, a.part, q.y, q.x, z);
 #pragma unroll
-        for (int k = 0; k < K; ++k) a.y[p * K + k] = store_as<TU>::from((a.dd ? dl * vc[k] : vc[k]) - z[k]);
-    };
-    window_products<K, TW, TU, A>(a.op, a.x, b, hv, prefetch, finish);
+    for (int k = 0; k < K; ++k) a.y[q.p * K + k] = store_as<TU>::from((a.dd ? dl * vc[k] : vc[k]) - z[k]);
 }
 
-// Power-method pass on the window layout (float vectors; see power_kernel).
+// Power-method pass on the window layout (float vectors; see power_kernel),
+// after window_part_kernel over x.
 struct WinPowerArgs {
     WinOp op;
+    const float* part;
     const float* x;
     float* y;
     const float* scale;
@@ -218,30 +305,26 @@ struct WinPowerArgs {
 
 template <typename TW>
 __global__ __launch_bounds__(256) void window_power_kernel(WinPowerArgs a) {
-    extern __shared__ unsigned char smem_raw[];
-    float* hv = reinterpret_cast<float*>(smem_raw);
-    const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
+    const WinPixel q = window_pixel(a.op);
     const float s = a.mode == 0 ? *a.scale : 1.0f;
-    float dl = 1.f, p0 = 0.f, p1 = 0.f;
-    auto prefetch = [&](bool ok, int64_t p) {
-        if (ok && a.dd) dl = a.dd[p];
-    };
-    auto finish = [&](bool ok, int64_t p, const float (&z)[1], const float (&vc)[1]) {
-        if (!ok) return;
-        const float xv = vc[0];
+    float p0 = 0.f, p1 = 0.f;
+    if (q.ok) {
+        const float dl = a.dd ? a.dd[q.p] : 1.f;
+        const float xv = a.x[q.p];
+        float z[1];
+        window_gather<1, float>(a.op, a.part, q.y, q.x, z);
         const float lx = (a.dd ? dl * xv : xv) - z[0];
         if (a.mode == 0) {
             const float yv = s * lx;
-            a.y[p] = yv;
+            a.y[q.p] = yv;
             p0 += yv * yv;
         } else {
             p0 += xv * lx;
             p1 += xv * xv;
         }
-    };
-    window_products<1, TW, float, float>(a.op, a.x, b, hv, prefetch, finish);
+    }
     float e[1] = {p0}, r[1] = {p1};
-    block_stats<1, 1>(e, r, 1, a.partials, (int64_t)gridDim.x, b);
+    block_stats<1, 1>(e, r, 1, a.partials, (int64_t)gridDim.x, q.b);
 }
 
 }  // namespace gl

@@ -67,8 +67,13 @@ def test_structure_and_counts(h, w, rw):
     assert info["n"] == h * w
     assert info["nnz"] == len(col)
     tiles = math.ceil(w / 64) * math.ceil(h / 4)
-    assert info["stored_entries"] == tiles * 256 * ((2 * rw + 1) ** 2 - 1)
-    assert info["stream_bytes"] == info["stored_entries"] * 4 + ((2 * rw + 1) ** 2 - 1) * 4
+    # each pair stored once: the first half of every pixel's window (F32: 4 per vector)
+    half = ((2 * rw + 1) ** 2 - 1) // 2
+    assert info["stored_entries"] == tiles * 256 * (-(-half // 4) * 4)
+    assert info["stream_bytes"] == info["stored_entries"] * 4
+    opb = _op(p, "bf16")  # 8 offsets per vector
+    assert opb.info()["stored_entries"] == tiles * 256 * (-(-half // 8) * 8)
+    opb.close()
 
 
 @pytest.mark.parametrize("laplacian", ["normalized", "unnormalized"])
@@ -104,7 +109,7 @@ def test_weights_f64_column_by_column(laplacian):
 def test_laplacian_apply(h, w, rw, store, K):
     p, _ = _problem(h, w, rw)
     store_w, store_u = store
-    if K * (64 + 2 * rw) * (4 + 2 * rw) * (8 if store_u == "f64" else 4) > 147456:
+    if 2 * K * (64 + 2 * rw) * (4 + rw) * (8 if store_u == "f64" else 4) > 147456:
         pytest.skip("K columns exceed the LDS of one block at this radius")
     rp_, col, ww = _graph(p)
     say(f"window laplacian {h}x{w} r={rw} store={store} K={K}")
@@ -209,6 +214,29 @@ def test_solve_parity(h, w, rw, store, tol):
     assert e_rel <= (1e-10 if store[1] == "f64" else 1e-4 if store == ("f32", "f32") else 2e-2)
     # Theorem 1: the energy does not increase over the DCA steps
     assert np.all(np.diff(eg[:, 0]) <= 1e-6 * np.abs(eg).max())
+
+
+@pytest.mark.parametrize("store", [("f32", "f32"), ("bf16", "f32"), ("f16", "f16")])
+def test_solve_bitwise_repeatable(store):
+    """Each stored weight serves both directions of its pair: a tile adds
+    w V_j into its own pixel and w V_i into the neighbour's cell of its region,
+    and the neighbour's sum gathers the regions of the tiles that cover it.
+    The order of all these additions is fixed (the window rows are phases
+    separated by barriers, and the regions are summed in tile order), so two
+    runs give the same bits.  Ragged 64 x 4 tiles, a window reaching four
+    tile rows up and one tile to each side."""
+    p, _ = _problem(37, 150, 12)
+    say(f"window solve run twice, store={store}")
+    op = _op(p, store[0])
+    lab = torch.from_numpy(p.labels).to(DEV)
+    outs = []
+    for _ in range(2):
+        U = torch.from_numpy(p.u0).to(DEV, DT[store[1]]).contiguous()
+        st = op.solve(lab, U, eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=p.outer,
+                      sweeps=p.sweeps, delta0=p.delta0, lambda_max=2.0)
+        outs.append((U.cpu().view(torch.uint8).numpy().copy(), st.cpu().numpy().copy()))
+    np.testing.assert_array_equal(outs[0][0], outs[1][0])
+    np.testing.assert_array_equal(outs[0][1], outs[1][1])
 
 
 @pytest.mark.timeout(900)
