@@ -36,21 +36,27 @@ TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_sweep_image2048_k4_traffic.j
 # sources whose change invalidates recorded counter traffic of the sweep kernel
 WINDOW_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "window_sweep_1024_r12_traffic.json")  # + _<weights>
 HBM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_sweep_image4096_k4_traffic.json")  # + _<weights>
-TRAFFIC_SOURCES = ["gl_grid.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
-                   "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_grid_f16.hip",
-                   "gl_unit_grid_bf16.hip", "gl_unit_grid_f32.hip", "gl_window.hpp"]
+# the sources of each sweep kernel whose counter summaries bench.py reads: a
+# summary counts only while their SHA-256 matches the one it was taken with
+TRAFFIC_SOURCES = {
+    "grid": ["gl_grid.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
+             "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_grid_f16.hip",
+             "gl_unit_grid_bf16.hip", "gl_unit_grid_f32.hip"],
+    "window": ["gl_window.hpp", "gl_window.hip", "gl_device.hpp", "gl_kernels.hpp",
+               "gl_launch_impl.hpp", "gl_internal.hpp", "gl_unit_f32.hip"],
+}
 
 
-def sweep_source_hash():
+def sweep_source_hash(kind="grid"):
     import hashlib
     h = hashlib.sha256()
-    for f in TRAFFIC_SOURCES:
+    for f in TRAFFIC_SOURCES[kind]:
         with open(os.path.join(ROOT, "paper_2303_14495_amd", "csrc", f), "rb") as fh:
             h.update(f.encode() + b"\0" + fh.read())
     return h.hexdigest()
 
 
-def recorded_traffic(workload_name, storage, path=TRAFFIC_FILE):
+def recorded_traffic(workload_name, storage, path=TRAFFIC_FILE, kind="grid"):
     """HBM bytes per sweep launch from the committed counter summary (FETCH_SIZE
     and WRITE_SIZE of the sweep kernel, each scaled by what the counter reads
     for a 1 GiB elementwise copy), or None when the summary is missing, is for
@@ -60,7 +66,7 @@ def recorded_traffic(workload_name, storage, path=TRAFFIC_FILE):
             t = json.load(fh)
     except (OSError, ValueError):
         return None
-    if (t.get("source_sha256") != sweep_source_hash() or t.get("workload") != workload_name
+    if (t.get("source_sha256") != sweep_source_hash(kind) or t.get("workload") != workload_name
             or t.get("storage") != storage):
         return None
     return (t["fetch_kib"] * t["fetch_scale"] + t["write_kib"] * t["write_scale"]) * 1024.0
@@ -448,7 +454,8 @@ def window_bench(dev, steps, warmup, reps):
                         "kernel": f"window_part_kernel<1, {store_w}, f32> + window_sweep_kernel<1, {store_w}, f32>",
                         "traffic": recorded_traffic(p.name, f"{store_w}/f32",
                                                     WINDOW_TRAFFIC_FILE.replace(
-                                                        ".json", f"_{store_w}.json"))}
+                                                        ".json", f"_{store_w}.json"),
+                                                    kind="window")}
         op.close()
         del U, U0, Uf
         torch.cuda.empty_cache()

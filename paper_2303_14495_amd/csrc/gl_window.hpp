@@ -33,6 +33,8 @@
 // image, and pixels of a ragged tile outside it, store weight 0.
 #pragma once
 
+#include <type_traits>
+
 #include "gl_kernels.hpp"
 
 namespace gl {
@@ -67,17 +69,21 @@ template <typename TU> struct WinPartArgs {
 template <int K, typename TW, typename TU>
 __global__ __launch_bounds__(256) void window_part_kernel(WinPartArgs<TU> a) {
     typedef typename acc_of<TU>::type A;
+    // V at the cell and the contributions added to it, read by one 64-bit LDS
+    // load (two 32-bit loads 8 bytes apart conflict on half the banks)
+    struct alignas(2 * sizeof(A)) A2 {
+        A v, s;
+    };
     constexpr int GS = 16 / (int)sizeof(TW);
     extern __shared__ unsigned char smem_raw[];
     const WinOp& op = a.op;
     const int S = kWinTX + 2 * op.r, plane = window_region(op.r);
-    A* hv = reinterpret_cast<A*>(smem_raw);  // V over the region, [k][cell]
-    A* acc = hv + K * plane;                 // contributions to the region's cells, [k][cell]
+    A2* hl = reinterpret_cast<A2*>(smem_raw);  // [cell][k]: one read returns both halves
     const int64_t b = xcd_remap(blockIdx.x, gridDim.x);
     const int ty = (int)(b / op.tiles_x), tx = (int)(b - (int64_t)ty * op.tiles_x);
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
 
-    // stage V over the region, kStage cells per lane in flight; clear the accumulator
+    // stage V over the region, kStage cells per lane in flight; clear the sums
     constexpr int kStage = 4;
     const int gx0 = tx * kWinTX - op.r, gy0 = ty * kWinTY - op.r;
     const float invS = 1.0f / (float)S;
@@ -103,10 +109,7 @@ __global__ __launch_bounds__(256) void window_part_kernel(WinPartArgs<TU> a) {
         for (int u = 0; u < kStage; ++u) {
             if (cell[u] < plane) {
 #pragma unroll
-                for (int k = 0; k < K; ++k) {
-                    hv[k * plane + cell[u]] = vals[u][k];
-                    acc[k * plane + cell[u]] = (A)0;
-                }
+                for (int k = 0; k < K; ++k) hl[cell[u] * K + k] = A2{vals[u][k], (A)0};
             }
         }
     }
@@ -115,61 +118,72 @@ __global__ __launch_bounds__(256) void window_part_kernel(WinPartArgs<TU> a) {
     const int base = (wave + op.r) * S + lane + op.r;  // the lane's own cell
     A vp[K];
 #pragma unroll
-    for (int k = 0; k < K; ++k) vp[k] = hv[k * plane + base];
+    for (int k = 0; k < K; ++k) vp[k] = hl[base * K + k].v;
     const int ng = window_groups(op.M, GS), mh = op.M / 2, side = 2 * op.r + 1;
     const u32x4* wp = static_cast<const u32x4*>(op.w) + b * (int64_t)ng * 256 + threadIdx.x;
     A z0[K], z1[K];
 #pragma unroll
     for (int k = 0; k < K; ++k) z0[k] = z1[k] = (A)0;
     // offset m of the first half: window row `row` and column `col` (dy = row - r,
-    // dx = col - r), i.e. the cell vbase + row * S + col
-    const int vbase = wave * S + lane;
-    int m = 0, row = 0, col = 0;
+    // dx = col - r), the cell vbase + rc with rc = row * S + col
+    A2* const vb = hl + (wave * S + lane) * K;
+    int m = 0, rc = 0, col = 0;
     auto ld = [&](int g) { return __builtin_nontemporal_load(wp + (int64_t)(g < ng ? g : ng - 1) * 256); };
-    auto step = [&](const u32x4& wq) {
+    // MASK: the vector may hold padding (offsets m >= mh: weight 0, added at the own cell)
+    auto step = [&](const u32x4& wq, auto mask) {
         TW we[GS];
         __builtin_memcpy(we, &wq, 16);
 #pragma unroll
         for (int e = 0; e < GS; ++e) {
-            // past the last offset (the padding of the last vectors and the
-            // vectors loaded ahead of the end): weight 0 at the own cell
-            const bool live = m < mh;
-            const int at = live ? vbase + row * S + col : base;
+            const bool live = !decltype(mask)::value || m < mh;
+            A2* const c = live ? vb + rc * K : hl + base * K;
             const A wv = live ? cvt<A>(we[e]) : (A)0;
 #pragma unroll
             for (int k = 0; k < K; ++k) {
-                if (e & 1) z1[k] += wv * hv[k * plane + at];
-                else z0[k] += wv * hv[k * plane + at];
-                acc[k * plane + at] += wv * vp[k];
+                const A2 t = c[k];
+                if (e & 1) z1[k] += wv * t.v;
+                else z0[k] += wv * t.v;
+                c[k].s = t.s + wv * vp[k];
+                // keep the own sum's FMA here: left to the scheduler, the FMAs of
+                // a whole vector wait at its end, and their operands held in
+                // registers cost three of the eight wavefronts a SIMD can hold
+                if (e & 1) asm volatile("" : "+v"(z1[k]));
+                else asm volatile("" : "+v"(z0[k]));
             }
             ++m;
+            ++rc;
             if (++col == side) {  // end of a phase: one window row done by all four wavefronts
                 col = 0;
-                ++row;
+                rc += S - side;
                 __syncthreads();
             }
         }
     };
+    typedef std::integral_constant<bool, false> Full;
+    typedef std::integral_constant<bool, true> Masked;
     u32x4 w0 = ld(0), w1 = ld(1), w2 = ld(2), w3 = ld(3);
-    for (int g = 0; g < ng; g += 4) {
-        step(w0);
+    int g = 0;
+    for (const int gq = (ng - 1) & ~3; g < gq; g += 4) {  // vectors without padding, four at a time
+        step(w0, Full());
         w0 = ld(g + 4);
-        step(w1);
+        step(w1, Full());
         w1 = ld(g + 5);
-        step(w2);
+        step(w2, Full());
         w2 = ld(g + 6);
-        step(w3);
+        step(w3, Full());
         w3 = ld(g + 7);
     }
+    // the last one to four vectors, already loaded
+    step(w0, Masked());
+    if (g + 1 < ng) step(w1, Masked());
+    if (g + 2 < ng) step(w2, Masked());
+    if (g + 3 < ng) step(w3, Masked());
     __syncthreads();
 #pragma unroll
-    for (int k = 0; k < K; ++k) acc[k * plane + base] += z0[k] + z1[k];
+    for (int k = 0; k < K; ++k) hl[base * K + k].s += z0[k] + z1[k];
     __syncthreads();
     A* out = a.part + b * (int64_t)plane * K;
-    for (int i = threadIdx.x; i < plane * K; i += 256) {
-        const int c = i / K, k = i - c * K;
-        out[i] = acc[k * plane + c];
-    }
+    for (int i = threadIdx.x; i < plane * K; i += 256) out[i] = hl[i].s;
 }
 
 // (W V) at pixel (y, x): the sum of the regions of the tiles that cover it
