@@ -40,7 +40,7 @@ HBM_TRAFFIC_FILE = os.path.join(ROOT, "profiles", "grid_sweep_image4096_k4_traff
 # summary counts only while their SHA-256 matches the one it was taken with
 TRAFFIC_SOURCES = {
     "grid": ["gl_grid.hpp", "gl_device.hpp", "gl_kernels.hpp", "gl_launch_impl.hpp",
-             "gl_internal.hpp", "gl_layout.hpp", "gl_layout.hip", "gl_unit_grid_f16.hip",
+             "gl_internal.hpp", "gl_layout.hpp", "gl_unit_grid_f16.hip",
              "gl_unit_grid_bf16.hip", "gl_unit_grid_f32.hip"],
     "window": ["gl_window.hpp", "gl_window.hip", "gl_device.hpp", "gl_kernels.hpp",
                "gl_launch_impl.hpp", "gl_internal.hpp", "gl_unit_f32.hip"],

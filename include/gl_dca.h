@@ -123,7 +123,7 @@ typedef enum gl_laplacian { GL_LAP_NORMALIZED = 0, GL_LAP_UNNORMALIZED = 1 } gl_
  *            entries as one byte of window offset (dy, dx) and the weight, in
  *            chunks of 8, and stages each 64 x 8 pixel tile's 15 x 15 window
  *            halo of the field in LDS; it takes no `order` and is built on
- *            the host (the CSR pattern is copied back once).  One call with K
+ *            the device.  One call with K
  *            columns needs K * 78 * 22 * (field element size: 2, 4 or 8
  *            bytes) <= 147456 of LDS and 22 * grid_width * K * (element
  *            size) < 2^32 bytes, both checked per call (GL_E_INVALID_ARG);
@@ -175,9 +175,10 @@ typedef struct gl_operator gl_operator;
  * what_ij = w_ij / (sqrt(d_i) sqrt(d_j)) rounded to `store_w` (GL_F64, GL_F32,
  * GL_BF16 or GL_F16), for L the rounded w_ij and the row sums of the stored
  * weights as the diagonal, in library-owned device memory, with its own copy of the
- * index arrays; the caller may free `graph`'s arrays after return.  With an
- * order or a tile request the index layout is built on the host (the CSR
- * pattern is copied back once).  Synchronises `stream`.  Errors: GL_E_INVALID_ARG, GL_E_BAD_GRAPH (message
+ * index arrays; the caller may free `graph`'s arrays after return.  Every
+ * index layout (direct, ordered, tile, grid) is built on the device; with an
+ * order or a tile request it takes about 16 bytes per nonzero of temporary
+ * device memory.  Synchronises `stream`.  Errors: GL_E_INVALID_ARG, GL_E_BAD_GRAPH (message
  * names the first defect), GL_E_DTYPE, GL_E_NOMEM, GL_E_HIP. */
 gl_status gl_operator_create(const gl_graph *graph, gl_dtype store_w, void *stream,
                              gl_operator **out);

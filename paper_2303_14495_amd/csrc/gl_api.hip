@@ -697,73 +697,62 @@ gl_status gl_operator_create(const gl_graph* g, gl_dtype store_w, void* stream, 
         return GL_OK;
     }
 
-    // processing order and/or tile layout: index layout built on the host
-    std::vector<int64_t> h_rp(g->n + 1);
-    std::vector<int32_t> h_col(g->nnz), h_order;
-    if (hipMemcpy(h_rp.data(), g->row_ptr, h_rp.size() * 8, hipMemcpyDeviceToHost) != hipSuccess ||
-        hipMemcpy(h_col.data(), g->col_idx, h_col.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
-        return cleanup_fail(GL_E_HIP, "copying the CSR pattern to the host failed");
-    if (g->order) {
-        h_order.resize(g->n);
-        if (hipMemcpy(h_order.data(), g->order, h_order.size() * 4, hipMemcpyDeviceToHost) != hipSuccess)
-            return cleanup_fail(GL_E_HIP, "copying the order to the host failed");
-        std::vector<char> seen(g->n, 0);
-        for (int64_t p = 0; p < g->n; ++p) {
-            const int32_t i = h_order[p];
-            if (i < 0 || i >= g->n || seen[i])
-                return cleanup_fail(GL_E_INVALID_ARG, "order is not a permutation of 0..n-1 (position " +
-                                                          std::to_string(p) + ")");
-            seen[i] = 1;
-        }
-    }
-    gl::HostLayout L;
+    // processing order and/or tile layout: index layout built on the device
+    gl::DeviceLayout L;
     std::string err;
     const int32_t halo_limit = store_w == GL_F64 ? 480 : gl::kTileHaloMax;
-    if (!gl::build_layout(g->n, h_rp.data(), h_col.data(), g->order ? h_order.data() : nullptr,
-                          g->layout != GL_LAYOUT_DIRECT, g->layout == GL_LAYOUT_TILE, halo_limit, L, err))
-        return cleanup_fail(GL_E_INVALID_ARG, err);
-    h_col.clear();
-    h_col.shrink_to_fit();
+    const gl::LayoutStatus ls = gl::build_layout(g->n, g->nnz, g->row_ptr, g->col_idx, g->order,
+                                                 g->layout != GL_LAYOUT_DIRECT, g->layout == GL_LAYOUT_TILE,
+                                                 halo_limit, s, L, err);
+    if (ls != gl::kLayoutOk) return cleanup_fail(ls == gl::kLayoutInvalid ? GL_E_INVALID_ARG : GL_E_HIP, err);
     op->layout = L.layout == 1 ? gl::LAYOUT_TILE : gl::LAYOUT_DIRECT;
     op->idx64 = false;
-    op->stored = (int64_t)L.src.size();
-    hipError_t e = hipSuccess;
-    if (g->order) e = upload(&op->order, h_order, s);
-    if (e == hipSuccess) e = upload((int32_t**)&op->rp, L.rp, s);
-    if (e == hipSuccess) e = upload(&d_src, L.src, s);
-    if (e == hipSuccess && op->layout == gl::LAYOUT_TILE) {
-        e = upload(&op->lcol, L.lcol, s);
-        if (e == hipSuccess) e = upload(&op->halo, L.halo, s);
-        if (e == hipSuccess) e = upload(&op->hp, L.hp, s);
+    op->stored = L.stored;
+    op->rp = L.rp;
+    d_src = L.src;
+    int32_t* d_pos_of = L.pos_of;
+    if (op->layout == gl::LAYOUT_TILE) {
+        op->lcol = L.lcol;
+        op->halo = L.halo;
+        op->hp = L.hp;
         op->hmax = L.hmax;
-        op->halo_total = (int64_t)L.halo.size();
-        op->nblocks = (int64_t)L.hp.size() - 1;
+        op->halo_total = L.halo_total;
+        op->nblocks = L.nblocks;
+    }
+    hipError_t e = hipSuccess;
+    if (g->order) {
+        e = hipMalloc((void**)&op->order, (size_t)g->n * 4);
+        if (e == hipSuccess) e = hipMemcpyAsync(op->order, g->order, (size_t)g->n * 4, hipMemcpyDeviceToDevice, s);
     }
     if (e == hipSuccess && op->layout == gl::LAYOUT_DIRECT)
         e = hipMalloc((void**)&op->col, (size_t)op->stored * 4 + 4);
     if (e == hipSuccess) e = hipMalloc(&op->w, (size_t)op->stored * sw + 16);
-    if (e != hipSuccess) return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
+    if (e != hipSuccess) {
+        (void)hipFree(d_pos_of);
+        return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
+    }
     op->bytes = (size_t)(g->n + 1) * 4 + (size_t)op->stored * sw + (size_t)g->n * 8 +
                 (g->order ? (size_t)g->n * 4 : 0) +
                 (op->layout == gl::LAYOUT_TILE ? (size_t)op->stored * 2 + (size_t)op->halo_total * 4 +
                                                      (size_t)(op->nblocks + 1) * 4
                                                : (size_t)op->stored * 4);
-    int32_t* d_pos_of = nullptr;
-    if (g->order && op->layout == gl::LAYOUT_DIRECT) {
-        std::vector<int32_t> pos_of(g->n);
-        for (int64_t p = 0; p < g->n; ++p) pos_of[h_order[p]] = (int32_t)p;
-        if (upload(&d_pos_of, pos_of, s) != hipSuccess || hipStreamSynchronize(s) != hipSuccess) {
-            (void)hipFree(d_pos_of);
-            return cleanup_fail(GL_E_NOMEM, "device allocation for the operator failed");
-        }
+    // the fill reads columns through pos_of only on the direct layout (the tile
+    // layout's halo already names positions)
+    if (op->layout == gl::LAYOUT_TILE) {
+        (void)hipFree(d_pos_of);
+        d_pos_of = nullptr;
     }
     if (g->weight_dtype == GL_F64) launch_fill_out<double>(op, g, d_src, d_pos_of, s);
     else launch_fill_out<float>(op, g, d_src, d_pos_of, s);
     const bool fill_ok = hipGetLastError() == hipSuccess && hipStreamSynchronize(s) == hipSuccess;
     (void)hipFree(d_pos_of);
     if (!fill_ok) return cleanup_fail(GL_E_HIP, "weight normalization failed");
-    if (op->layout == gl::LAYOUT_DIRECT && set_heavy_rows(op, L.rp.data(), s) != hipSuccess)
-        return cleanup_fail(GL_E_HIP, "heavy-row list failed");
+    if (op->layout == gl::LAYOUT_DIRECT) {
+        std::vector<int32_t> h_srp(g->n + 1);
+        if (hipMemcpy(h_srp.data(), op->rp, h_srp.size() * 4, hipMemcpyDeviceToHost) != hipSuccess ||
+            set_heavy_rows(op, h_srp.data(), s) != hipSuccess)
+            return cleanup_fail(GL_E_HIP, "heavy-row list failed");
+    }
     const gl_status su = finish_unnormalized(op, s);
     if (su != GL_OK) {
         const std::string m = gl_last_error();
