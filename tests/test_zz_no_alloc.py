@@ -65,6 +65,30 @@ def test_noalloc_equals_solve_on_shrinking_inputs():
     assert prev_need is not None
 
 
+def test_noalloc_window_operator():
+    """The window operator's products pass region sums between their two
+    kernels through the workspace: in the static array they overwrite what
+    the previous call left, larger image first."""
+    from synth.configs import window_problem
+    for (h, w, rw), (sw, su) in [((96, 200, 12), ("bf16", "f32")), ((37, 150, 12), ("f32", "f32"))]:
+        p = window_problem(h, w, rw, 2, seed=5)
+        say(f"noalloc vs gl_solve: window {h}x{w} r={rw} {sw}/{su}")
+        op = gl.Operator.window(torch.from_numpy(p.image).to(DEV, torch.float32), p.rw, p.rp, p.sigma,
+                                store_w=sw)
+        assert op.workspace_bytes(1, su) <= STATIC_BYTES
+        kw = dict(eps=p.eps, c=p.c, eta=p.eta, precond=p.precond, outer=p.outer, sweeps=p.sweeps,
+                  delta0=p.delta0, lambda_max=2.0)
+        lab = torch.from_numpy(np.ascontiguousarray(p.labels, dtype=np.int32)).to(DEV)
+        U0 = torch.from_numpy(np.ascontiguousarray(p.u0)).to(DEV, gl.TORCH_DTYPES[su]).contiguous()
+        Ua, Ub = U0.clone(), U0.clone()
+        st_a = op.solve(lab, Ua, **kw)
+        st_b = torch.full_like(st_a, float("nan"))
+        op.solve_noalloc(lab, Ub, st_b, **kw)
+        torch.cuda.synchronize()
+        assert torch.equal(Ua, Ub) and torch.equal(st_a, st_b)
+        op.close()
+
+
 def test_noalloc_repeated_call_same_result():
     # the same solve twice in a row: the second starts from the first one's
     # leftovers in the array and must not depend on them
