@@ -125,6 +125,25 @@ def test_laplacian_apply(h, w, rw, store, K):
     assert err <= tol
 
 
+@pytest.mark.parametrize("h,w,rw,K", [(37, 70, 12, 13), (24, 60, 27, 5)])
+def test_laplacian_at_the_lds_limit(h, w, rw, K):
+    """The most columns one call may take: 2 K (64 + 2r)(4 + r) floats of V and
+    accumulator fill 146 KB of LDS (r = 12, K = 13; r = 27, K = 5); one more
+    column is refused."""
+    p, _ = _problem(h, w, rw)
+    assert 2 * K * (64 + 2 * rw) * (4 + rw) * 4 <= 147456 < 2 * (K + 1) * (64 + 2 * rw) * (4 + rw) * 4
+    rp_, col, ww = _graph(p)
+    say(f"window laplacian at the LDS limit {h}x{w} r={rw} K={K}")
+    op = _op(p, "f32")
+    X = torch.from_numpy(np.random.default_rng(K).uniform(-1, 1, (p.n, K))).to(DEV, torch.float32).contiguous()
+    Y = op.laplacian_apply(X).double().cpu().numpy()
+    ref = gl_oracle.laplacian_apply(p.n, rp_, col, ww, X.double().cpu().numpy())
+    assert np.abs(Y - ref).max() <= 2e-6
+    X1 = torch.zeros((p.n, K + 1), dtype=torch.float32, device=DEV)
+    with pytest.raises(gl.GLError, match="LDS"):
+        op.laplacian_apply(X1)
+
+
 @pytest.mark.parametrize("h,w,rw", SHAPES[3:])
 def test_laplacian_thin_images(h, w, rw):
     p, _ = _problem(h, w, rw)
