@@ -190,21 +190,49 @@ __global__ __launch_bounds__(256) void window_part_kernel(WinPartArgs<TU> a) {
 // (tile rows from the pixel's own down, columns left to right).
 template <int K, typename A>
 __device__ __forceinline__ void window_gather(const WinOp& op, const A* __restrict__ part, int y, int x, A (&z)[K]) {
+    // a pixel lies in the regions of its own tile, of the tiles below it whose
+    // r rows above reach it, and of at most one horizontal neighbour of each
+    // (the left one when x mod 64 < r, the right one when x mod 64 >= 64 - r)
+    static_assert(2 * kWinMaxR < kWinTX, "one horizontal neighbour at most");
+    constexpr int NT = (kWinMaxR + 2 * kWinTY - 1) / kWinTY;  // tile rows that can cover a pixel
+    constexpr int B = K <= 4 ? 4 : (K <= 8 ? 2 : 1);           // tile rows requested at once
     const int S = kWinTX + 2 * op.r, plane = window_region(op.r);
     const int tiles_y = (op.height + kWinTY - 1) / kWinTY;
-    const int ty = y / kWinTY, tx = x / kWinTX;
+    const int ty = y / kWinTY, tx = x / kWinTX, xl = x - tx * kWinTX;
+    const int ty1 = min(tiles_y - 1, (y + op.r) / kWinTY);
+    const bool left = xl < op.r && tx > 0, right = xl >= kWinTX - op.r && tx + 1 < op.tiles_x;
+    const int ts = left ? tx - 1 : tx + 1;                        // the horizontal neighbour, if any
+    const int rxo = xl + op.r, rxs = left ? xl + kWinTX + op.r : xl - kWinTX + op.r;
 #pragma unroll
     for (int k = 0; k < K; ++k) z[k] = (A)0;
-    const int ty1 = min(tiles_y - 1, (y + op.r) / kWinTY);
-    for (int t2 = ty; t2 <= ty1; ++t2) {
-        const int ry = y - (t2 * kWinTY - op.r);
-        for (int t3 = tx - 1; t3 <= tx + 1; ++t3) {
-            const int rx = x - (t3 * kWinTX - op.r);
-            if (t3 < 0 || t3 >= op.tiles_x || rx < 0 || rx >= S) continue;
-            const A* src = part + ((int64_t)(t2 * op.tiles_x + t3) * plane + ry * S + rx) * K;
+    for (int t0 = 0; t0 < NT; t0 += B) {
+        // every request of the batch is issued before any is added; rows past
+        // the last covering one read the pixel's own cell and are not added
+        A own[B][K], side[B][K];
 #pragma unroll
-            for (int k = 0; k < K; ++k) z[k] += src[k];
+        for (int i = 0; i < B; ++i) {
+            const int t2 = ty + t0 + i;
+            const bool v = t2 <= ty1;
+            const int tr = v ? t2 : ty;
+            const int ry = y - (tr * kWinTY - op.r);
+            const int64_t rb = (int64_t)tr * op.tiles_x;
+            load_raw<K>(part + ((rb + tx) * plane + ry * S + rxo) * K, own[i]);
+            const bool vs = v && (left || right);
+            load_raw<K>(part + ((vs ? rb + ts : rb + tx) * plane + ry * S + (vs ? rxs : rxo)) * K, side[i]);
         }
+#pragma unroll
+        for (int i = 0; i < B; ++i) {
+            const bool v = ty + t0 + i <= ty1;
+#pragma unroll
+            for (int k = 0; k < K; ++k) {
+                A t = z[k];
+                t = v && left ? t + side[i][k] : t;
+                t = v ? t + own[i][k] : t;
+                t = v && right ? t + side[i][k] : t;
+                z[k] = t;
+            }
+        }
+        if (ty + t0 + B > ty1) break;
     }
 }
 
