@@ -156,6 +156,26 @@ def test_power_tile_vs_oracle():
     assert abs(rq - rq_o) <= 1e-4 * rq_o, (rq, rq_o)
 
 
+def test_ordered_auto_layout_falls_back_to_direct():
+    """A processing order on a graph without locality (the 784-dimensional
+    mixture in a random permutation): the device layout builder finds halos
+    beyond the tile limit and builds an ordered direct operator instead.  Each
+    row keeps its entries in CSR order, so the field equals the natural-order
+    operator's bit for bit."""
+    import paper_2303_14495_amd as gl
+    p = problem(3, small=True)
+    g = p.graph
+    perm = np.random.default_rng(11).permutation(p.n).astype(np.int32)
+    say(f"ordered auto layout, random permutation, n={p.n}")
+    op = gl.Operator(g.row_ptr.to(DEV), g.col.to(DEV), g.weight.to(DEV).to(torch.float64), store_w="f32",
+                     layout="auto", order=torch.from_numpy(perm).to(DEV))
+    assert op.info()["layout"] == "direct"
+    ref = make_operator(p, "f32", use_order=False)
+    Ua = gpu_solve(p, "f32", "f32", op=op, stats=False)[0]
+    Ub = gpu_solve(p, "f32", "f32", op=ref, stats=False)[0]
+    assert np.array_equal(Ua, Ub)
+
+
 def test_tile_request_rejected_without_locality():
     import paper_2303_14495_amd as gl
     p = problem(4, small=True)
