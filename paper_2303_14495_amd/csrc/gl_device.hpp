@@ -244,6 +244,51 @@ template <typename A> __device__ __forceinline__ A xor_add(A x, int off) {
     return x + __shfl_xor(x, off, 64);
 }
 
+// The value of lane (lane ^ OFF) within aligned groups of 2 OFF lanes, by DPP
+// moves where the pattern allows (every lane of the wavefront must be active):
+// OFF = 1, 2 quad permutes; 4 = mirror within 8 lanes, then reverse within 4
+// (i ^ 7 ^ 3); 8 = mirror within 16, then within 8 (i ^ 15 ^ 7); larger
+// offsets cross DPP rows and use the LDS permute.
+template <int OFF> __device__ __forceinline__ int xor_partner32(int v) {
+    if constexpr (OFF == 1) return dpp_mov<0xb1, 0xf>(v);
+    else if constexpr (OFF == 2) return dpp_mov<0x4e, 0xf>(v);
+    else if constexpr (OFF == 4) return dpp_mov<0x1b, 0xf>(dpp_mov<0x141, 0xf>(v));
+    else if constexpr (OFF == 8) return dpp_mov<0x141, 0xf>(dpp_mov<0x140, 0xf>(v));
+    else return __shfl_xor(v, OFF, 64);
+}
+
+template <int OFF, typename A> __device__ __forceinline__ A xor_partner(A x) {
+    if constexpr (sizeof(A) == 4) {
+        return __builtin_bit_cast(A, xor_partner32<OFF>(__builtin_bit_cast(int, x)));
+    } else {
+        const uint64_t u = __builtin_bit_cast(uint64_t, x);
+        const uint32_t lo = (uint32_t)xor_partner32<OFF>((int)(uint32_t)u);
+        const uint32_t hi = (uint32_t)xor_partner32<OFF>((int)(uint32_t)(u >> 32));
+        return __builtin_bit_cast(A, ((uint64_t)hi << 32) | lo);
+    }
+}
+
+// Butterfly over aligned groups of G = 2^log2G lanes (4 <= G <= 64): every
+// lane of a group ends with the group's sum of z[k], added in the same order
+// as the shuffle form z[k] += shfl_xor(z[k], off) for off = G/2, ..., 1.
+template <int L2, int K, typename A> __device__ __forceinline__ void butterfly_fixed(A (&z)[K]) {
+    if constexpr (L2 > 0) {
+#pragma unroll
+        for (int k = 0; k < K; ++k) z[k] += xor_partner<(1 << (L2 - 1))>(z[k]);
+        butterfly_fixed<L2 - 1, K>(z);
+    }
+}
+
+template <int K, typename A> __device__ __forceinline__ void group_butterfly(A (&z)[K], int log2G) {
+    switch (log2G) {
+        case 2: butterfly_fixed<2, K>(z); break;
+        case 3: butterfly_fixed<3, K>(z); break;
+        case 4: butterfly_fixed<4, K>(z); break;
+        case 5: butterfly_fixed<5, K>(z); break;
+        default: butterfly_fixed<6, K>(z); break;
+    }
+}
+
 // Sum the per-lane column partials of a 256-thread block.  Lane q of every group
 // holds columns q, q+G, ...; after the cross-group swaps lanes 0..G-1 of each
 // wavefront hold the wavefront's sums, which four LDS slots combine in wavefront

@@ -71,10 +71,7 @@ __device__ __forceinline__ void row_gather(const OffT* __restrict__ rp, const in
 #pragma unroll
     for (int k = 0; k < K; ++k) z[k] = (A)0;
     if (row < n) row_accumulate<K>(col, w, V, rp[row] + (OffT)q, rp[row + 1], G, z);
-    for (int off = G >> 1; off > 0; off >>= 1) {
-#pragma unroll
-        for (int k = 0; k < K; ++k) z[k] += __shfl_xor(z[k], off, 64);
-    }
+    group_butterfly<K>(z, __builtin_ctz((unsigned)G));
 }
 
 // The fused update of column k of row `node` (Prop. 1, Section 3.1) from
@@ -158,10 +155,7 @@ __device__ __forceinline__ void sweep_block(const SweepArgs<TW, TU, OffT>& a, in
 #pragma unroll
         for (int k = 0; k < K; ++k) z[k] = (A)0;
         if (live) row_accumulate<K>(a.col, a.w, a.vin, beg[t] + (OffT)q, end[t], G, z);
-        for (int off = G >> 1; off > 0; off >>= 1) {
-#pragma unroll
-            for (int k = 0; k < K; ++k) z[k] += __shfl_xor(z[k], off, 64);
-        }
+        group_butterfly<K>(z, a.g.log2G);
         if (live) {
 #pragma unroll
             for (int c = 0; c < CPL; ++c) {
